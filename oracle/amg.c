@@ -1,0 +1,255 @@
+/*
+ * Oracle: algebraic multigrid on the pressure block A_pp.
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * The paper names AMG for the pressure stage M(A_pp)^-1 of Algorithm 2 (the
+ * "Multi-stage preconditioner" section) without fixing a variant.  This
+ * oracle uses the reading adopted for both sides:
+ *   - A_pp = the (pressure-equation, pressure) entry of every decoupled
+ *     cell-cell block, restriction Pi_r of Eq 34 applied to rows and columns;
+ *   - strength: j is a strong neighbour of i when -a_ij > 0 and
+ *     -a_ij >= theta * max_{k != i} (-a_ik);
+ *   - pairwise matching by handshakes: in each round every unmatched row
+ *     proposes its strongest unmatched strong neighbour (largest -a_ij,
+ *     ties to the smaller index); mutual proposals become pairs; rows left
+ *     after the last round are singletons;
+ *   - two matching passes per level (the second on the first Galerkin
+ *     product) give aggregates of at most four rows; aggregates are numbered
+ *     by their smallest member;
+ *   - piecewise-constant prolongation P, Galerkin coarse matrix A_c = P^T A P
+ *     summed in ascending fine row, then stored column order;
+ *   - l1-Jacobi smoothing (d_i = sum_j |a_ij|), one sweep before and after
+ *     the coarse correction, zero initial guess, V-cycle;
+ *   - coarsest level solved by dense LU with partial pivoting.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include "oracle.h"
+
+/* Pi_r A Pi_p restricted to reservoir rows/columns: scalar CSR of a00. */
+void om_extract_pressure(const om_bsr *A, int ncell, om_csr *P)
+{
+    int nnz = 0;
+    for (int i = 0; i < ncell; i++)
+        for (int z = A->rp[i]; z < A->rp[i + 1]; z++)
+            if (A->col[z] < ncell) nnz++;
+    P->n = ncell; P->nnz = nnz;
+    P->rp = (int *)malloc(sizeof(int) * (ncell + 1));
+    P->col = (int *)malloc(sizeof(int) * (nnz > 0 ? nnz : 1));
+    P->val = (double *)malloc(sizeof(double) * (nnz > 0 ? nnz : 1));
+    nnz = 0;
+    P->rp[0] = 0;
+    for (int i = 0; i < ncell; i++) {
+        for (int z = A->rp[i]; z < A->rp[i + 1]; z++)
+            if (A->col[z] < ncell) {
+                P->col[nnz] = A->col[z];
+                P->val[nnz] = A->val[4 * z];
+                nnz++;
+            }
+        P->rp[i + 1] = nnz;
+    }
+}
+
+void om_strength_match(const om_csr *A, double theta, int rounds, int *match)
+{
+    int n = A->n;
+    int *prop = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    double *thr = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    for (int i = 0; i < n; i++) {
+        double mx = 0.0;
+        for (int z = A->rp[i]; z < A->rp[i + 1]; z++)
+            if (A->col[z] != i && -A->val[z] > mx) mx = -A->val[z];
+        thr[i] = theta * mx;
+        match[i] = -1;
+    }
+    for (int r = 0; r < rounds; r++) {
+        for (int i = 0; i < n; i++) {
+            prop[i] = -1;
+            if (match[i] >= 0) continue;
+            double best = 0.0;
+            for (int z = A->rp[i]; z < A->rp[i + 1]; z++) {
+                int j = A->col[z];
+                double s = -A->val[z];
+                if (j == i || match[j] >= 0 || !(s > 0.0) || s < thr[i]) continue;
+                if (s > best) { best = s; prop[i] = j; }
+            }
+        }
+        for (int i = 0; i < n; i++) {
+            int j = prop[i];
+            if (match[i] < 0 && j >= 0 && prop[j] == i) match[i] = j;
+        }
+    }
+    free(prop); free(thr);
+}
+
+/* Aggregate numbering from a matching: leaders are singletons and the
+ * smaller member of each pair, numbered in ascending order. */
+static int number_aggregates(int n, const int *match, int *agg)
+{
+    int nc = 0;
+    for (int i = 0; i < n; i++)
+        if (match[i] < 0 || i < match[i]) agg[i] = nc++;
+    for (int i = 0; i < n; i++)
+        if (match[i] >= 0 && match[i] < i) agg[i] = agg[match[i]];
+    return nc;
+}
+
+static int cmp_int(const void *a, const void *b)
+{
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* A_c = P^T A P for the piecewise-constant P of `agg` (fine row -> aggregate). */
+void om_galerkin(const om_csr *A, const int *agg, int nc, om_csr *Ac)
+{
+    int n = A->n;
+    /* members of each aggregate in ascending fine order */
+    int *mp = (int *)calloc(nc + 1, sizeof(int));
+    int *mem = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    for (int i = 0; i < n; i++) mp[agg[i] + 1]++;
+    for (int I = 0; I < nc; I++) mp[I + 1] += mp[I];
+    int *fill = (int *)malloc(sizeof(int) * (nc > 0 ? nc : 1));
+    memcpy(fill, mp, sizeof(int) * nc);
+    for (int i = 0; i < n; i++) mem[fill[agg[i]]++] = i;
+    /* sparse accumulator per coarse row */
+    int *marker = (int *)malloc(sizeof(int) * (nc > 0 ? nc : 1));
+    double *acc = (double *)malloc(sizeof(double) * (nc > 0 ? nc : 1));
+    for (int J = 0; J < nc; J++) marker[J] = -1;
+    int cap = A->nnz > 0 ? A->nnz : 1;
+    Ac->rp = (int *)malloc(sizeof(int) * (nc + 1));
+    Ac->col = (int *)malloc(sizeof(int) * cap);
+    Ac->val = (double *)malloc(sizeof(double) * cap);
+    Ac->n = nc;
+    int nz = 0;
+    Ac->rp[0] = 0;
+    for (int I = 0; I < nc; I++) {
+        int start = nz;
+        for (int q = mp[I]; q < mp[I + 1]; q++) {
+            int i = mem[q];
+            for (int z = A->rp[i]; z < A->rp[i + 1]; z++) {
+                int J = agg[A->col[z]];
+                if (marker[J] != I) { marker[J] = I; acc[J] = 0.0; Ac->col[nz++] = J; }
+                acc[J] += A->val[z];
+            }
+        }
+        qsort(Ac->col + start, nz - start, sizeof(int), cmp_int);
+        for (int z = start; z < nz; z++) Ac->val[z] = acc[Ac->col[z]];
+        Ac->rp[I + 1] = nz;
+    }
+    Ac->nnz = nz;
+    free(mp); free(mem); free(fill); free(marker); free(acc);
+}
+
+static void csr_copy(om_csr *d, const om_csr *s)
+{
+    d->n = s->n; d->nnz = s->nnz;
+    d->rp = (int *)malloc(sizeof(int) * (s->n + 1));
+    d->col = (int *)malloc(sizeof(int) * (s->nnz > 0 ? s->nnz : 1));
+    d->val = (double *)malloc(sizeof(double) * (s->nnz > 0 ? s->nnz : 1));
+    memcpy(d->rp, s->rp, sizeof(int) * (s->n + 1));
+    memcpy(d->col, s->col, sizeof(int) * s->nnz);
+    memcpy(d->val, s->val, sizeof(double) * s->nnz);
+}
+
+int om_amg_setup(om_amg *H, const om_csr *A0, double theta, int max_coarse, int max_levels,
+                 int rounds)
+{
+    memset(H, 0, sizeof(*H));
+    if (max_levels > 24) max_levels = 24;
+    csr_copy(&H->A[0], A0);
+    int l = 0;
+    while (H->A[l].n > max_coarse && l + 1 < max_levels) {
+        const om_csr *A = &H->A[l];
+        int n = A->n;
+        int *m1 = (int *)malloc(sizeof(int) * n), *a1 = (int *)malloc(sizeof(int) * n);
+        om_strength_match(A, theta, rounds, m1);
+        int n1 = number_aggregates(n, m1, a1);
+        om_csr A1;
+        om_galerkin(A, a1, n1, &A1);
+        int *m2 = (int *)malloc(sizeof(int) * (n1 > 0 ? n1 : 1));
+        int *a2 = (int *)malloc(sizeof(int) * (n1 > 0 ? n1 : 1));
+        om_strength_match(&A1, theta, rounds, m2);
+        int n2 = number_aggregates(n1, m2, a2);
+        if (n2 >= n) { /* no coarsening progress */
+            om_csr_free(&A1);
+            free(m1); free(a1); free(m2); free(a2);
+            break;
+        }
+        om_galerkin(&A1, a2, n2, &H->A[l + 1]);
+        H->agg[l] = (int *)malloc(sizeof(int) * n);
+        for (int i = 0; i < n; i++) H->agg[l][i] = a2[a1[i]];
+        om_csr_free(&A1);
+        free(m1); free(a1); free(m2); free(a2);
+        l++;
+    }
+    H->nlev = l + 1;
+    for (int k = 0; k < H->nlev; k++) {
+        const om_csr *A = &H->A[k];
+        H->l1[k] = (double *)malloc(sizeof(double) * (A->n > 0 ? A->n : 1));
+        for (int i = 0; i < A->n; i++) {
+            double s = 0.0;
+            for (int z = A->rp[i]; z < A->rp[i + 1]; z++) s += fabs(A->val[z]);
+            H->l1[k][i] = s;
+        }
+        H->wr[k] = (double *)malloc(sizeof(double) * (A->n > 0 ? A->n : 1));
+        H->wx[k] = (double *)malloc(sizeof(double) * (A->n > 0 ? A->n : 1));
+        H->wb[k] = (double *)malloc(sizeof(double) * (A->n > 0 ? A->n : 1));
+    }
+    const om_csr *C = &H->A[H->nlev - 1];
+    int nc = C->n;
+    H->ncoarse = nc;
+    H->lu = (double *)calloc((size_t)nc * nc > 0 ? (size_t)nc * nc : 1, sizeof(double));
+    H->piv = (int *)malloc(sizeof(int) * (nc > 0 ? nc : 1));
+    for (int i = 0; i < nc; i++)
+        for (int z = C->rp[i]; z < C->rp[i + 1]; z++) H->lu[(size_t)i * nc + C->col[z]] += C->val[z];
+    return om_dense_lu(nc, H->lu, H->piv);
+}
+
+static void csr_resid(const om_csr *A, const double *b, const double *x, double *r)
+{
+    for (int i = 0; i < A->n; i++) {
+        double s = b[i];
+        for (int z = A->rp[i]; z < A->rp[i + 1]; z++) s -= A->val[z] * x[A->col[z]];
+        r[i] = s;
+    }
+}
+
+static void vcycle(const om_amg *H, int l, const double *b, double *x)
+{
+    const om_csr *A = &H->A[l];
+    int n = A->n;
+    if (l == H->nlev - 1) {
+        memcpy(x, b, sizeof(double) * n);
+        om_dense_lu_solve(n, H->lu, H->piv, x);
+        return;
+    }
+    const double *d = H->l1[l];
+    double *r = H->wr[l];
+    for (int i = 0; i < n; i++) x[i] = b[i] / d[i];              /* pre-smooth, zero guess */
+    csr_resid(A, b, x, r);
+    int nc = H->A[l + 1].n;
+    double *bc = H->wb[l + 1], *xc = H->wx[l + 1];
+    for (int I = 0; I < nc; I++) bc[I] = 0.0;
+    for (int i = 0; i < n; i++) bc[H->agg[l][i]] += r[i];       /* restriction P^T r */
+    vcycle(H, l + 1, bc, xc);
+    for (int i = 0; i < n; i++) x[i] += xc[H->agg[l][i]];       /* prolongation P xc */
+    csr_resid(A, b, x, r);
+    for (int i = 0; i < n; i++) x[i] += r[i] / d[i];             /* post-smooth */
+}
+
+void om_amg_vcycle(const om_amg *H, const double *b, double *x)
+{
+    vcycle(H, 0, b, x);
+}
+
+void om_amg_free(om_amg *H)
+{
+    for (int k = 0; k < H->nlev; k++) {
+        om_csr_free(&H->A[k]);
+        free(H->l1[k]); free(H->agg[k]); free(H->wr[k]); free(H->wx[k]); free(H->wb[k]);
+    }
+    free(H->lu); free(H->piv);
+    memset(H, 0, sizeof(*H));
+}
