@@ -1,0 +1,259 @@
+/*
+ * r2p: MI355X (gfx950) library for the Newton-step linear solve of a fully
+ * implicit two-phase (oil-water) finite-difference reservoir model.
+ *
+ * Method: Liu, Shen, Chen, Wang, Yang, Chen, "A Parallel Simulator for Massive
+ * Reservoir Models Utilizing Distributed-Memory Parallel Systems",
+ * arXiv 1701.06254.  Citations below name the paper's sections and
+ * equations.
+ *
+ * Conventions (all entry points)
+ *   - Return value: 0 = success, > 0 = soft failure (see each entry point),
+ *     < 0 = error (R2P_E*).  r2p_last_error() gives a message for the last
+ *     non-zero status on the calling thread.  No C++ exception crosses this
+ *     interface.
+ *   - Pointers whose name ends in _host point to host memory; every other
+ *     array pointer is device memory on the model's device, owned by the
+ *     caller unless stated otherwise.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; calls that must read scalars back synchronise
+ *     that stream and say so.
+ *   - Field units: ft, psi, mD, cP, bbl, STB/day, days.
+ *   - Cells are in natural order c = i + nx*(j + ny*k), k counted downward
+ *     from the top layer.  A state vector has N = 2*(n + nw) doubles,
+ *     interleaved per cell: x[2c] = oil pressure p, x[2c+1] = water
+ *     saturation s_w; then per well x[2(n+w)] = bottom-hole pressure p_b and
+ *     x[2(n+w)+1] = a dummy unknown that is always 0.  This is the paper's
+ *     unknown vector (p; s_w; p_b) of Eq 19-23 under a fixed permutation
+ *     (p_c -> 2c, s_c -> 2c+1, p_b,w -> 2(n+w)).
+ *   - Handles are not thread safe; one handle is used by one thread at a time.
+ */
+#ifndef R2P_H
+#define R2P_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    R2P_OK = 0,
+    R2P_NOT_CONVERGED = 1,   /* iterative method stopped at its iteration limit */
+    R2P_BREAKDOWN = 2,       /* Krylov breakdown before convergence */
+    R2P_EINVAL = -1,         /* invalid argument */
+    R2P_ENOMEM = -2,         /* device allocation failed */
+    R2P_EHIP = -3,           /* HIP runtime error */
+    R2P_ENAN = -4,           /* non-finite value met */
+    R2P_ESTATE = -5,         /* call out of order (e.g. solve before setup) */
+    R2P_ESINGULAR = -6       /* singular pivot block in a factorisation */
+};
+
+/* Well kinds and controls: the constraints of Eq 11-14. */
+enum { R2P_INJECTOR = 0, R2P_PRODUCER = 1 };
+enum { R2P_BHP = 0, R2P_WRATE = 1, R2P_ORATE = 2, R2P_LRATE = 3 };
+
+typedef struct r2p_model r2p_model;
+typedef struct r2p_jacobian r2p_jacobian;
+typedef struct r2p_cpr r2p_cpr;
+
+/* Model description ("Two-phase oil-water flow model", Eq 1-14).
+ * Every array is host memory and is copied on create.
+ *   kx/ky/kz_host[n]  permeability (mD, > 0); phi_host[n] porosity in (0,1).
+ *   consts[12] = {beta_c (Darcy factor, 0.001127), alpha_c (ft^3/bbl),
+ *                 rho_o, rho_w (reference densities, lbm/ft^3),
+ *                 p_ref (reference pressure, psi), z_ref (its depth, ft),
+ *                 c_o, c_w, c_r (compressibilities, 1/psi),
+ *                 mu_o, mu_w (viscosities, cP), grav (1 on, 0 off)}.
+ *   Wells: w_ptr_host[nw+1] offsets into w_cell_host (perforated cells, the
+ *   first is the reference depth z_b); kind, control and target (STB/day for
+ *   rates, psi for BHP; rate targets are magnitudes, injection positive);
+ *   radius (ft) and skin.  A cell may be perforated by at most one well. */
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz;    /* cell sizes, ft */
+    double top;           /* depth of the top-layer cell centres, ft */
+    const double *kx_host, *ky_host, *kz_host, *phi_host;
+    double consts[12];
+    int nw;
+    const int *w_ptr_host, *w_cell_host, *w_kind_host, *w_ctrl_host;
+    const double *w_target_host, *w_rw_host, *w_skin_host;
+    int device;           /* HIP device ordinal */
+} r2p_model_desc;
+
+/* Options of the CPR preconditioner ("Matrix decoupling strategy",
+ * "Local potential reordering technique", "Multi-stage preconditioner"). */
+enum { R2P_DEC_NONE = 0, R2P_DEC_QI = 1, R2P_DEC_ABF = 2 };
+enum { R2P_ORDER_NATURAL = 0, R2P_ORDER_POTENTIAL = 1 };
+enum { R2P_CPR_TWO_STAGE = 0, R2P_CPR_FPF = 1 };
+enum { R2P_FP64 = 0, R2P_FP32 = 1 };
+typedef struct {
+    int decouple;      /* R2P_DEC_*: D^-1 of Eq 29 (Quasi-IMPES or ABF) */
+    int order;         /* R2P_ORDER_*: local order of each RAS subdomain (Eq 30-32) */
+    int form;          /* R2P_CPR_*: two-stage, or Algorithm 2 (FPF) */
+    int px, py;        /* RAS subdomains: px x py tiles of the x-y plane, full z columns (px*py <= 64) */
+    int overlap;       /* RAS overlap in block-graph layers (>= 0) */
+    double theta;      /* AMG strength threshold (0.25) */
+    int max_coarse;    /* AMG: stop coarsening at this many rows (<= 2048) */
+    int max_levels;    /* AMG: at most this many levels (<= 24) */
+    int match_rounds;  /* AMG: handshake rounds per pairwise matching (4) */
+    int agg_passes;    /* AMG: aggregation passes per level (1 or 2; 2 gives aggregates of ~4) */
+    int precision;     /* R2P_FP64, or R2P_FP32: AMG and ILU stored and applied in FP32 */
+} r2p_cpr_opts;
+
+typedef struct {
+    int restart;       /* FGMRES restart length m (1..64) */
+    int maxit;         /* iteration limit */
+    double rtol;       /* relative residual target on the decoupled system */
+} r2p_solve_opts;
+
+typedef struct {
+    int iterations;
+    int status;        /* return code of the solve */
+    double relres;     /* true ||D^-1(b - A y)|| / ||D^-1 b|| at exit */
+    double ms_total;   /* host wall time of the call */
+    int reorth;        /* Gram-Schmidt passes repeated (selective second pass) */
+} r2p_solve_info;
+
+enum { R2P_FORCING_FIXED = 0, R2P_FORCING_EW = 1 };
+typedef struct {
+    int max_newton;    /* Newton iteration limit (20) */
+    double tol;        /* scaled residual tolerance (1e-8) */
+    int forcing;       /* R2P_FORCING_FIXED: each solve to lin.rtol; R2P_FORCING_EW: Eq 26, second choice */
+    double ds_max;     /* largest saturation change per Newton iteration (0.2; <= 0 disables) */
+    r2p_cpr_opts cpr;
+    r2p_solve_opts lin;
+} r2p_newton_opts;
+
+#define R2P_HIST 32
+typedef struct {
+    int status;              /* 0 converged, 1 not converged (x unchanged) */
+    int newton_its;
+    int linear_its;
+    int used_guess;          /* 1 if x_guess was taken as the first iterate */
+    double res_hist[R2P_HIST];   /* scaled residual norm per Newton iteration */
+    double ms_assemble, ms_setup, ms_solve, ms_total;
+} r2p_newton_info;
+
+/* ----------------------------------------------------------------- model */
+
+/* Copy the model to the device and derive geometry (harmonic two-point
+ * transmissibilities), Peaceman well indices and well reference depths.
+ * Errors: R2P_EINVAL (bad sizes, k <= 0, phi outside (0,1), perforation out
+ * of range or a cell perforated twice), R2P_ENOMEM, R2P_EHIP. */
+int r2p_model_create(const r2p_model_desc *desc, r2p_model **out);
+int r2p_model_destroy(r2p_model *m);
+/* n cells, nw wells, nperf perforations; N = 2*(n+nw). */
+int r2p_model_sizes(const r2p_model *m, int *n_host, int *nw_host, int *nperf_host);
+
+/* x[N] <- oil-hydrostatic state through (p_ref, z_ref) with s_w = 0; BHP
+ * wells at their target, rate wells at their top perforation's pressure. */
+int r2p_initial_state(r2p_model *m, double *x, void *stream);
+
+/* --------------------------------------------------------------- Jacobian */
+
+/* Library-owned Jacobian storage for one model (reused across calls). */
+int r2p_jacobian_create(r2p_model *m, r2p_jacobian **out);
+int r2p_jacobian_destroy(r2p_jacobian *J);
+
+/* Residual and Jacobian of the discrete system F(x) = 0 (Eq 15-23): J <-
+ * dF/dx at x, b[N] <- -F(x), for the backward-Euler step x_old -> x of
+ * length dt days.  Also records the oil potential of every cell (Eq 5) for
+ * the reordering.  Asynchronous on `stream`.  x, x_old, b: device, length N.
+ * Errors: R2P_EINVAL (dt <= 0, NULL). */
+int r2p_assemble_jacobian(r2p_model *m, const double *x, const double *x_old, double dt,
+                          r2p_jacobian *J, double *b, void *stream);
+
+/* Scaled infinity norm of -b (the Newton stopping test): max over cells of
+ * |F_a| dt / PV (PV = V phi / alpha_c) and over wells of |F_w|/|target|.
+ * Synchronises `stream`.  NaN in b gives R2P_ENAN. */
+int r2p_residual_norm(r2p_model *m, const double *b, double dt, double *norm_host, void *stream);
+
+/* y[N] <- J x[N] with J as currently stored (decoupled once set up). */
+int r2p_spmv(r2p_jacobian *J, const double *x, double *y, void *stream);
+
+/* Copy J to host block-CSR (2x2 blocks, row-major, columns ascending, cell
+ * rows then well rows).  With rp_host == NULL only *nnzb_host is set.
+ * Synchronises `stream`. */
+int r2p_jacobian_export(r2p_jacobian *J, int *nnzb_host, int *rp_host, int *col_host,
+                        double *val_host, void *stream);
+
+/* -------------------------------------------------------------------- CPR */
+
+int r2p_cpr_create(r2p_cpr **out);
+int r2p_cpr_destroy(r2p_cpr *P);
+
+/* Build the CPR preconditioner for an assembled J: decouple J in place
+ * (Eq 29; the row operators are kept to transform right-hand sides), then
+ * set up block ILU(0) on every overlapped subdomain in its local order (RAS
+ * stage) and the aggregation AMG hierarchy of the pressure block A_pp
+ * (restriction Pi_r of Eq 34).  Synchronises `stream` (level counts and
+ * coarse sizes are read back).  J must have been assembled since its last
+ * setup.  Errors: R2P_ESTATE, R2P_EINVAL, R2P_ESINGULAR, R2P_ENOMEM. */
+int r2p_setup_cpr(r2p_jacobian *J, const r2p_cpr_opts *opts, r2p_cpr *P, void *stream);
+
+/* z[N] <- M^-1 f[N] for the decoupled system (two-stage form or Algorithm 2). */
+int r2p_cpr_apply(r2p_cpr *P, const double *f, double *z, void *stream);
+
+/* Stage solvers on their own, for inspection:
+ *   x_p[n] <- one AMG V-cycle on A_pp for right-hand side f_p[n];
+ *   y[N]   <- RAS with block ILU(0) subdomain solves (restricted scatter). */
+int r2p_amg_vcycle(r2p_cpr *P, const double *f_p, double *x_p, void *stream);
+int r2p_ras_apply(r2p_cpr *P, const double *r, double *y, void *stream);
+
+/* Inspection of the AMG hierarchy (host copies; synchronises `stream`).
+ * r2p_amg_info: number of levels and rows/nonzeros of level l.
+ * r2p_amg_export_level: CSR of level l (columns ascending), its l1 row sums,
+ * and agg[i] = row of level l+1 holding row i (NULL allowed; unset on the
+ * last level). */
+int r2p_amg_info(r2p_cpr *P, int level, int *nlev_host, int *n_host, int *nnz_host);
+int r2p_amg_export_level(r2p_cpr *P, int level, int *rp_host, int *col_host, double *val_host,
+                         double *l1_host, int *agg_host, void *stream);
+
+/* Inspection of the RAS factors (host copies; synchronises `stream`).
+ * r2p_ras_info: subdomain count, and for subdomain s its local rows,
+ * factor blocks (off-diagonal L and U blocks) and level count.
+ * r2p_ras_export: for subdomain s, glob[m] = global block row of each local
+ * row (level order), level[m], owned[m], dinv[m][4] = inverse of U's
+ * diagonal block; and for each off-diagonal factor block e:
+ * erow[e], ecol[e] global block row/column and eval[e][4] (L for columns
+ * before the row in the local order, else U). */
+int r2p_ras_info(r2p_cpr *P, int s, int *nsub_host, int *m_host, int *nblk_host,
+                 int *nlevels_host);
+int r2p_ras_export(r2p_cpr *P, int s, int *glob_host, int *level_host, unsigned char *owned_host,
+                   double *dinv_host, int *erow_host, int *ecol_host, double *eval_host,
+                   void *stream);
+
+/* ------------------------------------------------------------------ solve */
+
+/* Solve A y = b for the Jacobian J (original, not decoupled, right-hand
+ * side; D^-1 is applied inside: D^-1 A y = D^-1 b, Eq 29) by right
+ * preconditioned flexible GMRES(restart) from y = 0 with the CPR
+ * preconditioner P.  Classical Gram-Schmidt with a selective second pass;
+ * convergence on the true residual of the decoupled system.
+ * Synchronous.  Returns 0, R2P_NOT_CONVERGED (y holds the last iterate) or
+ * R2P_BREAKDOWN, or an error. */
+int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y,
+              const r2p_solve_opts *opts, r2p_solve_info *info, void *stream);
+
+/* One implicit time step x^n -> x^{n+1} by Newton's method ("Nonlinear
+ * methods", Algorithm 1): assemble, test the scaled residual, set up CPR,
+ * solve, update x += y (saturation change limited to ds_max, then clipped
+ * to [0,1]).  Standard Newton solves every system to lin.rtol; with
+ * R2P_FORCING_EW the tolerance follows the second forcing term of Eq 26,
+ * clipped to [0.01, 0.1].  x_guess (device, may be NULL): a first iterate
+ * to try; it is used only if its scaled residual is below that of x^n.
+ * x: device, in x^n, out x^{n+1}.  Synchronous.  Returns 0, or
+ * R2P_NOT_CONVERGED with x unchanged (the caller shortens dt). */
+int r2p_newton_step(r2p_model *m, double *x, double dt, const double *x_guess,
+                    const r2p_newton_opts *opts, r2p_newton_info *info, void *stream);
+
+/* Default options: QI, potential order, two-stage, 4x4 subdomains, overlap
+ * 1, theta 0.25, coarse 500, 20 levels, 4 rounds, 2 passes, FP64; FGMRES(30) to 1e-8
+ * with 300 iterations; Newton 20 iterations to 1e-8, ds_max 0.2. */
+void r2p_default_newton_opts(r2p_newton_opts *o);
+
+const char *r2p_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

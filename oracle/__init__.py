@@ -62,13 +62,14 @@ class CprOpts(C.Structure):
     _fields_ = [("decouple", C.c_int), ("order", C.c_int), ("form", C.c_int),
                 ("px", C.c_int), ("py", C.c_int), ("overlap", C.c_int),
                 ("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int),
-                ("match_rounds", C.c_int), ("exact_stages", C.c_int)]
+                ("match_rounds", C.c_int), ("agg_passes", C.c_int), ("exact_stages", C.c_int)]
 
 
 def cpr_opts(decouple=DEC_QI, order=ORD_POTENTIAL, form=CPR_TWO_STAGE, px=4, py=4, overlap=1,
-             theta=0.25, max_coarse=500, max_levels=20, match_rounds=4, exact_stages=0):
+             theta=0.25, max_coarse=500, max_levels=20, match_rounds=4, agg_passes=2,
+             exact_stages=0):
     return CprOpts(decouple, order, form, px, py, overlap, theta, max_coarse, max_levels,
-                   match_rounds, exact_stages)
+                   match_rounds, agg_passes, exact_stages)
 
 
 def lib():
@@ -102,6 +103,7 @@ def lib():
     L.om_dense_lu_solve.argtypes = [C.c_int, f64p, i32p, f64p]
     L.om_strength_match.argtypes = [C.POINTER(Csr), C.c_double, C.c_int, i32p]
     L.om_galerkin.argtypes = [C.POINTER(Csr), i32p, C.c_int, C.POINTER(Csr)]
+    L.om_aggregate.argtypes = [C.POINTER(Csr), C.c_double, C.c_int, i32p]
     L.om_csr_free.argtypes = [C.POINTER(Csr)]
     L.om_api_cpr_create.argtypes = [C.POINTER(Bsr), vp, f64p, C.POINTER(CprOpts),
                                     C.POINTER(C.c_int)]
@@ -117,7 +119,7 @@ def lib():
     L.om_api_ras_copy_sub.argtypes = [vp, C.c_int, i32p, u8p, i32p, i32p, f64p, f64p]
     L.om_api_ras_apply.argtypes = [vp, f64p, f64p]
     L.om_api_amg_create.argtypes = [C.POINTER(Csr), C.c_double, C.c_int, C.c_int, C.c_int,
-                                    C.POINTER(C.c_int)]
+                                    C.c_int, C.POINTER(C.c_int)]
     L.om_api_amg_create.restype = vp
     L.om_api_amg_destroy.argtypes = [vp]
     L.om_api_amg_h_nlev.argtypes = [vp]
@@ -355,6 +357,13 @@ def extract_pressure(A, ncell):
     return CsrMatrix(rows, cols, vals)
 
 
+def aggregate(A, theta=0.25, rounds=4):
+    """One aggregation pass (matching, joins, numbering): (agg, number of aggregates)."""
+    agg = np.zeros(A.n, np.int32)
+    nc = lib().om_aggregate(C.byref(A.cstruct()), theta, rounds, agg)
+    return agg, nc
+
+
 def strength_match(A, theta=0.25, rounds=4):
     m = np.zeros(A.n, np.int32)
     lib().om_strength_match(C.byref(A.cstruct()), theta, rounds, m)
@@ -375,11 +384,11 @@ def galerkin(A, agg, nc):
 class Amg:
     """Standalone AMG hierarchy on a scalar CSR matrix."""
 
-    def __init__(self, A, theta=0.25, max_coarse=500, max_levels=20, rounds=4):
+    def __init__(self, A, theta=0.25, max_coarse=500, max_levels=20, rounds=4, passes=2):
         rc = C.c_int()
         self._A = A.cstruct()
         self.h = lib().om_api_amg_create(C.byref(self._A), theta, max_coarse, max_levels,
-                                         rounds, C.byref(rc))
+                                         rounds, passes, C.byref(rc))
         if rc.value:
             raise ValueError("coarsest matrix singular")
 

@@ -12,10 +12,12 @@
  *   - pairwise matching by handshakes: in each round every unmatched row
  *     proposes its strongest unmatched strong neighbour (largest -a_ij,
  *     ties to the smaller index); mutual proposals become pairs; rows left
- *     after the last round are singletons;
- *   - two matching passes per level (the second on the first Galerkin
- *     product) give aggregates of at most four rows; aggregates are numbered
- *     by their smallest member;
+ *     after the last round join the pair of their strongest strong
+ *     neighbour that is in a pair (ties to the smaller index), or stay
+ *     singletons when there is none;
+ *   - `passes` aggregation passes per level (each on the Galerkin product of
+ *     the previous one); aggregates are numbered by their leader (the
+ *     smaller row of a pair, or the singleton);
  *   - piecewise-constant prolongation P, Galerkin coarse matrix A_c = P^T A P
  *     summed in ascending fine row, then stored column order;
  *   - l1-Jacobi smoothing (d_i = sum_j |a_ij|), one sweep before and after
@@ -83,15 +85,47 @@ void om_strength_match(const om_csr *A, double theta, int rounds, int *match)
     free(prop); free(thr);
 }
 
-/* Aggregate numbering from a matching: leaders are singletons and the
- * smaller member of each pair, numbered in ascending order. */
-static int number_aggregates(int n, const int *match, int *agg)
+/* Rows left unmatched after the handshake rounds join the pair of their
+ * strongest strong neighbour that is in a pair (ties to the smaller index);
+ * a row with no such neighbour stays a singleton.  jt[i] = that neighbour
+ * or -1. */
+void om_join_targets(const om_csr *A, double theta, const int *match, int *jt)
 {
+    for (int i = 0; i < A->n; i++) {
+        double mx = 0.0;
+        for (int z = A->rp[i]; z < A->rp[i + 1]; z++)
+            if (A->col[z] != i && -A->val[z] > mx) mx = -A->val[z];
+        double thr = theta * mx;
+        jt[i] = -1;
+        if (match[i] >= 0) continue;
+        double best = 0.0;
+        for (int z = A->rp[i]; z < A->rp[i + 1]; z++) {
+            int j = A->col[z];
+            double s = -A->val[z];
+            if (j == i || match[j] < 0 || !(s > 0.0) || s < thr) continue;
+            if (s > best) { best = s; jt[i] = j; }
+        }
+    }
+}
+
+/* Aggregates of one pass: pairs plus the rows that join them, and the
+ * remaining singletons, numbered by their leader (the smaller row
+ * of the pair, or the singleton). */
+int om_aggregate(const om_csr *A, double theta, int rounds, int *agg)
+{
+    int n = A->n;
+    int *match = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    int *jt = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    om_strength_match(A, theta, rounds, match);
+    om_join_targets(A, theta, match, jt);
     int nc = 0;
     for (int i = 0; i < n; i++)
-        if (match[i] < 0 || i < match[i]) agg[i] = nc++;
+        if ((match[i] >= 0 && i < match[i]) || (match[i] < 0 && jt[i] < 0)) agg[i] = nc++;
     for (int i = 0; i < n; i++)
         if (match[i] >= 0 && match[i] < i) agg[i] = agg[match[i]];
+    for (int i = 0; i < n; i++)
+        if (match[i] < 0 && jt[i] >= 0) agg[i] = agg[jt[i]];
+    free(match); free(jt);
     return nc;
 }
 
@@ -154,34 +188,38 @@ static void csr_copy(om_csr *d, const om_csr *s)
 }
 
 int om_amg_setup(om_amg *H, const om_csr *A0, double theta, int max_coarse, int max_levels,
-                 int rounds)
+                 int rounds, int passes)
 {
     memset(H, 0, sizeof(*H));
     if (max_levels > 24) max_levels = 24;
     csr_copy(&H->A[0], A0);
     int l = 0;
+    if (passes < 1) passes = 1;
     while (H->A[l].n > max_coarse && l + 1 < max_levels) {
-        const om_csr *A = &H->A[l];
-        int n = A->n;
-        int *m1 = (int *)malloc(sizeof(int) * n), *a1 = (int *)malloc(sizeof(int) * n);
-        om_strength_match(A, theta, rounds, m1);
-        int n1 = number_aggregates(n, m1, a1);
-        om_csr A1;
-        om_galerkin(A, a1, n1, &A1);
-        int *m2 = (int *)malloc(sizeof(int) * (n1 > 0 ? n1 : 1));
-        int *a2 = (int *)malloc(sizeof(int) * (n1 > 0 ? n1 : 1));
-        om_strength_match(&A1, theta, rounds, m2);
-        int n2 = number_aggregates(n1, m2, a2);
-        if (n2 >= n) { /* no coarsening progress */
-            om_csr_free(&A1);
-            free(m1); free(a1); free(m2); free(a2);
+        int n = H->A[l].n;
+        int *agg = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+        for (int i = 0; i < n; i++) agg[i] = i;
+        om_csr cur;
+        csr_copy(&cur, &H->A[l]);
+        int nc = n;
+        for (int p = 0; p < passes; p++) {     /* successive passes on Galerkin products */
+            int *a = (int *)malloc(sizeof(int) * (cur.n > 0 ? cur.n : 1));
+            int m = om_aggregate(&cur, theta, rounds, a);
+            om_csr next;
+            om_galerkin(&cur, a, m, &next);
+            for (int i = 0; i < n; i++) agg[i] = a[agg[i]];
+            om_csr_free(&cur);
+            cur = next;
+            nc = m;
+            free(a);
+        }
+        if (nc >= n) { /* no coarsening progress */
+            om_csr_free(&cur);
+            free(agg);
             break;
         }
-        om_galerkin(&A1, a2, n2, &H->A[l + 1]);
-        H->agg[l] = (int *)malloc(sizeof(int) * n);
-        for (int i = 0; i < n; i++) H->agg[l][i] = a2[a1[i]];
-        om_csr_free(&A1);
-        free(m1); free(a1); free(m2); free(a2);
+        H->A[l + 1] = cur;
+        H->agg[l] = agg;
         l++;
     }
     H->nlev = l + 1;
@@ -200,6 +238,7 @@ int om_amg_setup(om_amg *H, const om_csr *A0, double theta, int max_coarse, int 
     const om_csr *C = &H->A[H->nlev - 1];
     int nc = C->n;
     H->ncoarse = nc;
+    if (nc > 4096) return -2;    /* coarsening stalled: no dense solve of that size */
     H->lu = (double *)calloc((size_t)nc * nc > 0 ? (size_t)nc * nc : 1, sizeof(double));
     H->piv = (int *)malloc(sizeof(int) * (nc > 0 ? nc : 1));
     for (int i = 0; i < nc; i++)

@@ -97,7 +97,7 @@ typedef struct {
     int decouple, order, form;
     int px, py, overlap;
     double theta;         /* AMG strength threshold */
-    int max_coarse, max_levels, match_rounds;
+    int max_coarse, max_levels, match_rounds, agg_passes;
     int exact_stages;     /* 1: RAS and V-cycle replaced by dense solves (pin of Alg 2) */
 } om_cpr_opts;
 
@@ -158,12 +158,14 @@ void om_bilu0_solve(const om_bsr *LU, const double *dinv, const int *diag, doubl
 
 /* amg.c */
 int  om_amg_setup(om_amg *H, const om_csr *A0, double theta, int max_coarse, int max_levels,
-                  int rounds);
+                  int rounds, int passes);
 void om_amg_vcycle(const om_amg *H, const double *b, double *x);
 void om_amg_free(om_amg *H);
 void om_extract_pressure(const om_bsr *A, int ncell, om_csr *App);
 void om_strength_match(const om_csr *A, double theta, int rounds, int *match);
 void om_galerkin(const om_csr *A, const int *agg, int nc, om_csr *Ac);
+void om_join_targets(const om_csr *A, double theta, const int *match, int *jt);
+int  om_aggregate(const om_csr *A, double theta, int rounds, int *agg);
 
 /* solver.c */
 int  om_cpr_setup(om_cpr *P, const om_bsr *Adec, const om_model *mdl, const double *x,

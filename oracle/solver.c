@@ -52,7 +52,7 @@ int om_cpr_setup(om_cpr *P, const om_bsr *A, const om_model *mdl, const double *
     } else {
         rc = om_ras_setup(&P->ras, A, mdl, x, o->px, o->py, o->overlap, o->order);
         if (!rc) rc = om_amg_setup(&P->amg, &App, o->theta, o->max_coarse, o->max_levels,
-                                   o->match_rounds);
+                                   o->match_rounds, o->agg_passes);
     }
     om_csr_free(&App);
     return rc;

@@ -1,0 +1,677 @@
+// Aggregation AMG on the pressure block A_pp (the M(A_pp)^-1 stage of the
+// "Multi-stage preconditioner", Algorithm 2, with restriction Pi_r of Eq 34).
+//
+// The paper names AMG without fixing a variant.  Reading used here:
+// strength -a_ij >= theta * max_{k!=i}(-a_ik) with -a_ij > 0; pairwise
+// matching by handshakes (each unmatched row proposes its strongest
+// unmatched strong neighbour, ties to the smaller index; mutual proposals
+// pair up; `match_rounds` rounds); rows still unmatched join the pair of
+// their strongest strong neighbour that is in a pair, else stay singletons;
+// aggregates numbered by their leader (smaller row of the pair or the singleton); `agg_passes` passes per
+// level, each on the Galerkin product of the previous one; piecewise-constant
+// prolongation and Galerkin coarse matrices summed in ascending fine row and
+// stored column order; l1-Jacobi smoothing (d_i = sum_j |a_ij|), one sweep
+// before and after the coarse correction; V-cycle; the coarsest level is
+// solved with its explicit inverse, computed once per set-up by dense LU
+// with partial pivoting in FP64.
+//
+// Every set-up decision (strength, matching, joins, numbering) is integer
+// work on values summed in a fixed order, so the hierarchy is reproducible.
+// Compiled without floating-point contraction.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "r2p_impl.h"
+
+constexpr int BS = 256;
+
+// ------------------------------------------------------- level 0 = A_pp
+__global__ void k_app_count(Phys P, int *cnt) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.n) return;
+    int nxy = P.nx * P.ny;
+    int i = c % P.nx, j = (c / P.nx) % P.ny, k = c / nxy;
+    cnt[c] = 1 + (i > 0) + (i + 1 < P.nx) + (j > 0) + (j + 1 < P.ny) + (k > 0) + (k + 1 < P.nz);
+}
+
+__global__ void k_app_cols(Phys P, const int *rp, int *col, int *slot) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P.n) return;
+    int nxy = P.nx * P.ny;
+    int i = c % P.nx, j = (c / P.nx) % P.ny, k = c / nxy;
+    int z = rp[c];
+    const int order[7] = {5, 3, 1, 0, 2, 4, 6};
+    bool ex[7] = {true, i > 0, i + 1 < P.nx, j > 0, j + 1 < P.ny, k > 0, k + 1 < P.nz};
+    for (int oi = 0; oi < 7; oi++) {
+        int sl = order[oi];
+        if (!ex[sl]) continue;
+        col[z] = c + slot_offset(sl, P.nx, nxy);
+        slot[z] = sl;
+        z++;
+    }
+}
+
+__global__ void k_app_vals(int n, const int *rp, const int *slot, const double2 *vp, double *val) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    for (int z = rp[c]; z < rp[c + 1]; z++) val[z] = vp[(long)slot[z] * n + c].x;
+}
+
+// ------------------------------------------------------------- matching
+__global__ void k_strength_thr(int n, const int *rp, const int *col, const double *val,
+                               double theta, double *thr, int *match) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double mx = 0.0;
+    for (int z = rp[i]; z < rp[i + 1]; z++)
+        if (col[z] != i && -val[z] > mx) mx = -val[z];
+    thr[i] = theta * mx;
+    match[i] = -1;
+}
+
+__global__ void k_propose(int n, const int *rp, const int *col, const double *val,
+                          const double *thr, const int *match, int *prop) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int best_j = -1;
+    if (match[i] < 0) {
+        double best = 0.0;
+        for (int z = rp[i]; z < rp[i + 1]; z++) {
+            int j = col[z];
+            double s = -val[z];
+            if (j == i || match[j] >= 0 || !(s > 0.0) || s < thr[i]) continue;
+            if (s > best) { best = s; best_j = j; }
+        }
+    }
+    prop[i] = best_j;
+}
+
+__global__ void k_accept(int n, const int *prop, int *match) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int j = prop[i];
+    if (match[i] < 0 && j >= 0 && prop[j] == i) match[i] = j;
+}
+
+// Unmatched rows: strongest strong neighbour that is in a pair (or -1).
+__global__ void k_join(int n, const int *rp, const int *col, const double *val, const double *thr,
+                       const int *match, int *jt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int best_j = -1;
+    if (match[i] < 0) {
+        double best = 0.0;
+        for (int z = rp[i]; z < rp[i + 1]; z++) {
+            int j = col[z];
+            double s = -val[z];
+            if (j == i || match[j] < 0 || !(s > 0.0) || s < thr[i]) continue;
+            if (s > best) { best = s; best_j = j; }
+        }
+    }
+    jt[i] = best_j;
+}
+
+__global__ void k_leader_flag(int n, const int *match, const int *jt, int *flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int j = match[i];
+    flag[i] = (j >= 0 && i < j) || (j < 0 && jt[i] < 0);
+}
+
+__global__ void k_number(int n, const int *match, const int *jt, const int *cid, int *agg) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int j = match[i];
+    int lead;
+    if (j >= 0) lead = i < j ? i : j;
+    else if (jt[i] < 0) lead = i;
+    else {
+        int k = jt[i];
+        int mk = match[k];
+        lead = k < mk ? k : mk;
+    }
+    agg[i] = cid[lead];
+}
+
+// Composition of a pass with the aggregation so far: agg[i] <- a[agg[i]].
+__global__ void k_compose(int n, const int *a, int *agg) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) agg[i] = a[agg[i]];
+}
+
+__global__ void k_iota(int n, int *a) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = i;
+}
+
+// Member lists (CSR) of the aggregates, ascending within each list: the
+// rows are stably sorted by aggregate, then every list start is marked.
+__global__ void k_member_keys(int n, const int *agg, unsigned *key, unsigned *val) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { key[i] = (unsigned)agg[i]; val[i] = (unsigned)i; }
+}
+
+__global__ void k_member_ptr(int n, int nc, const unsigned *key, int *mptr) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n && (k == 0 || key[k] != key[k - 1])) mptr[key[k]] = k;
+    if (k == 0) mptr[nc] = n;
+}
+
+// ------------------------------------------------------------- Galerkin
+// A_c = P^T A P by expand-sort-compress: every stored entry a_ij becomes the
+// term (agg(i), agg(j), a_ij); the terms are stably sorted by coarse column
+// and then by coarse row, so equal (I, J) terms stay in ascending (row,
+// stored column) order and are summed in that order.
+__global__ void k_gal_expand(int n, const int *rp, const int *agg, unsigned *keyI,
+                             const int *col, unsigned *keyJ, unsigned *idx) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned I = (unsigned)agg[i];
+    for (int z = rp[i]; z < rp[i + 1]; z++) {
+        keyI[z] = I;
+        keyJ[z] = (unsigned)agg[col[z]];
+        idx[z] = (unsigned)z;
+    }
+}
+
+__global__ void k_gather_u(int m, const unsigned *idx, const unsigned *src, unsigned *dst) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < m) dst[k] = src[idx[k]];
+}
+
+__global__ void k_gal_flags(int m, const unsigned *idx, const unsigned *keyI,
+                            const unsigned *keyJz, int *flag) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    bool f = k == 0;
+    if (!f) f = keyI[k] != keyI[k - 1] || keyJz[idx[k]] != keyJz[idx[k - 1]];
+    flag[k] = f;
+}
+
+__global__ void k_gal_compress(int m, int nc, const unsigned *idx, const unsigned *keyI,
+                               const unsigned *keyJz, const int *uidx, const double *val,
+                               int *rpc, int *colc, double *valc, int nnzc) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) rpc[nc] = nnzc;
+    if (k >= m) return;
+    bool first = k == 0 || keyI[k] != keyI[k - 1] || keyJz[idx[k]] != keyJz[idx[k - 1]];
+    if (!first) return;
+    int u = uidx[k];
+    unsigned I = keyI[k], J = keyJz[idx[k]];
+    double s = 0.0;
+    for (int t = k; t < m && keyI[t] == I && keyJz[idx[t]] == J; t++) s += val[idx[t]];
+    colc[u] = (int)J;
+    valc[u] = s;
+    if (k == 0 || keyI[k - 1] != I) rpc[I] = u;
+}
+
+__global__ void k_l1(int n, const int *rp, const double *val, double *l1) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int z = rp[i]; z < rp[i + 1]; z++) s += fabs(val[z]);
+    l1[i] = s;
+}
+
+template <class T>
+__global__ void k_castv(long n, const double *a, T *b) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (T)a[i];
+}
+
+// ------------------------------------------------------------- coarsest
+__global__ void k_to_dense(int n, const int *rp, const int *col, const double *val, double *a) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int j = 0; j < n; j++) a[(long)i * n + j] = 0.0;
+    for (int z = rp[i]; z < rp[i + 1]; z++) a[(long)i * n + col[z]] += val[z];
+}
+
+// LU with partial pivoting (largest magnitude, ties to the smaller row) by
+// one workgroup, then the inverse column by column; the inverse is written
+// column-major so the coarse solve reads it coalesced.
+__global__ __launch_bounds__(1024) void k_dense_lu_inv(int n, double *a, int *piv, double *invT,
+                                                     int *status) {
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    int tid = threadIdx.x, nt = blockDim.x;
+    for (int k = 0; k < n; k++) {
+        double best = -1.0;
+        int bi = n;
+        for (int i = k + tid; i < n; i += nt) {
+            double v = fabs(a[(long)i * n + k]);
+            if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+        }
+        sv[tid] = best;
+        si[tid] = bi;
+        __syncthreads();
+        for (int w = nt / 2; w > 0; w >>= 1) {
+            if (tid < w) {
+                double v = sv[tid + w];
+                int ii = si[tid + w];
+                if (v > sv[tid] || (v == sv[tid] && ii < si[tid])) { sv[tid] = v; si[tid] = ii; }
+            }
+            __syncthreads();
+        }
+        int p = si[0];
+        double pv = sv[0];
+        __syncthreads();
+        if (tid == 0) piv[k] = p;
+        if (pv == 0.0 || pv != pv) {
+            if (tid == 0) *status = 1;
+            return;
+        }
+        if (p != k)
+            for (int j = tid; j < n; j += nt) {
+                double t = a[(long)k * n + j];
+                a[(long)k * n + j] = a[(long)p * n + j];
+                a[(long)p * n + j] = t;
+            }
+        __syncthreads();
+        double inv = 1.0 / a[(long)k * n + k];
+        for (int i = k + 1 + tid; i < n; i += nt) a[(long)i * n + k] = a[(long)i * n + k] * inv;
+        __syncthreads();
+        long rem = (long)(n - k - 1) * (n - k - 1);
+        for (long t = tid; t < rem; t += nt) {
+            int i = k + 1 + (int)(t / (n - k - 1)), j = k + 1 + (int)(t % (n - k - 1));
+            double l = a[(long)i * n + k];
+            if (l != 0.0) a[(long)i * n + j] -= l * a[(long)k * n + j];
+        }
+        __syncthreads();
+    }
+    // inverse: column c of A^-1 solves A x = e_c
+    for (int c = tid; c < n; c += nt) {
+        double *x = invT + (long)c * n;
+        for (int i = 0; i < n; i++) x[i] = i == c ? 1.0 : 0.0;
+        for (int k = 0; k < n; k++) {
+            int p = piv[k];
+            if (p != k) { double t = x[k]; x[k] = x[p]; x[p] = t; }
+        }
+        for (int i = 0; i < n; i++) {
+            double s = x[i];
+            for (int j = 0; j < i; j++) s -= a[(long)i * n + j] * x[j];
+            x[i] = s;
+        }
+        for (int i = n - 1; i >= 0; i--) {
+            double s = x[i];
+            for (int j = i + 1; j < n; j++) s -= a[(long)i * n + j] * x[j];
+            x[i] = s / a[(long)i * n + i];
+        }
+    }
+}
+
+// --------------------------------------------------------------- set-up
+// Member lists (CSR, ascending) of the nc aggregates of agg[0..n).
+static int build_members(r2p_cpr *P, int n, const int *agg, int nc, DBuf<int> &mptr,
+                         DBuf<int> &mem, hipStream_t s) {
+    DBuf<unsigned> key, kt, vt;
+    DBuf<int> hist;
+    R2P_TRY(mptr.ensure(nc + 1));
+    R2P_TRY(mem.ensure(n));
+    R2P_TRY(key.ensure(n));
+    R2P_TRY(kt.ensure(n));
+    R2P_TRY(vt.ensure(n));
+    unsigned *val = (unsigned *)mem.p;
+    k_member_keys<<<r2p_blocks(n, BS), BS, 0, s>>>(n, agg, key.p, val);
+    R2P_LAUNCH();
+    R2P_TRY(r2p_sort_pairs(key.p, val, kt.p, vt.p, n, r2p_bits_for(nc), hist, P->iscratch,
+                           P->pin, s));
+    k_member_ptr<<<r2p_blocks(n, BS), BS, 0, s>>>(n, nc, key.p, mptr.p);
+    R2P_LAUNCH();
+    R2P_HIP(hipStreamSynchronize(s));
+    return 0;
+}
+
+static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, const double *val,
+                    const int *agg, int nc, DBuf<int> &rpc, DBuf<int> &colc, DBuf<double> &valc,
+                    int *nnzc, hipStream_t s) {
+    DBuf<unsigned> keyI, keyJz, idx, kt, vt, keyIs;
+    DBuf<int> flag, hist;
+    R2P_TRY(keyI.ensure(nnz));
+    R2P_TRY(keyJz.ensure(nnz));
+    R2P_TRY(keyIs.ensure(nnz));
+    R2P_TRY(idx.ensure(nnz));
+    R2P_TRY(kt.ensure(nnz));
+    R2P_TRY(vt.ensure(nnz));
+    R2P_TRY(flag.ensure(nnz + 1));
+    k_gal_expand<<<r2p_blocks(n, BS), BS, 0, s>>>(n, rp, agg, keyI.p, col, keyJz.p, idx.p);
+    R2P_LAUNCH();
+    int bits = r2p_bits_for(nc);
+    // stable by coarse column, then stable by coarse row
+    R2P_HIP(hipMemcpyAsync(kt.p, keyJz.p, sizeof(unsigned) * nnz, hipMemcpyDeviceToDevice, s));
+    R2P_HIP(hipMemcpyAsync(keyIs.p, kt.p, sizeof(unsigned) * nnz, hipMemcpyDeviceToDevice, s));
+    R2P_TRY(r2p_sort_pairs(keyIs.p, idx.p, kt.p, vt.p, nnz, bits, hist, P->iscratch, P->pin, s));
+    k_gather_u<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, idx.p, keyI.p, keyIs.p);
+    R2P_LAUNCH();
+    R2P_TRY(r2p_sort_pairs(keyIs.p, idx.p, kt.p, vt.p, nnz, bits, hist, P->iscratch, P->pin, s));
+    k_gal_flags<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, idx.p, keyIs.p, keyJz.p, flag.p);
+    R2P_LAUNCH();
+    R2P_HIP(hipMemsetAsync(flag.p + nnz, 0, sizeof(int), s));
+    int nnz_c = 0;
+    R2P_TRY(r2p_scan_int(flag.p, flag.p, nnz + 1, &nnz_c, P->iscratch, P->pin, s));
+    R2P_TRY(rpc.ensure(nc + 1));
+    R2P_TRY(colc.ensure(nnz_c));
+    R2P_TRY(valc.ensure(nnz_c));
+    k_gal_compress<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, nc, idx.p, keyIs.p, keyJz.p, flag.p,
+                                                     val, rpc.p, colc.p, valc.p, nnz_c);
+    R2P_LAUNCH();
+    R2P_HIP(hipStreamSynchronize(s));
+    *nnzc = nnz_c;
+    return 0;
+}
+
+// One aggregation pass: agg (row -> aggregate) and the aggregate count.
+static int aggregate_pass(r2p_cpr *P, int n, const int *rp, const int *col, const double *val,
+                          DBuf<int> &agg, int *nc, hipStream_t s) {
+    DBuf<double> thr;
+    DBuf<int> match, prop, flag, jt;
+    R2P_TRY(thr.ensure(n));
+    R2P_TRY(match.ensure(n));
+    R2P_TRY(prop.ensure(n));
+    R2P_TRY(jt.ensure(n));
+    R2P_TRY(flag.ensure(n + 1));
+    int nb = r2p_blocks(n, BS);
+    k_strength_thr<<<nb, BS, 0, s>>>(n, rp, col, val, P->o.theta, thr.p, match.p);
+    R2P_LAUNCH();
+    for (int r = 0; r < P->o.match_rounds; r++) {
+        k_propose<<<nb, BS, 0, s>>>(n, rp, col, val, thr.p, match.p, prop.p);
+        R2P_LAUNCH();
+        k_accept<<<nb, BS, 0, s>>>(n, prop.p, match.p);
+        R2P_LAUNCH();
+    }
+    k_join<<<nb, BS, 0, s>>>(n, rp, col, val, thr.p, match.p, jt.p);
+    R2P_LAUNCH();
+    k_leader_flag<<<nb, BS, 0, s>>>(n, match.p, jt.p, flag.p);
+    R2P_LAUNCH();
+    R2P_HIP(hipMemsetAsync(flag.p + n, 0, sizeof(int), s));
+    int cnt = 0;
+    R2P_TRY(r2p_scan_int(flag.p, flag.p, n + 1, &cnt, P->iscratch, P->pin, s));
+    R2P_TRY(agg.ensure(n));
+    k_number<<<nb, BS, 0, s>>>(n, match.p, jt.p, flag.p, agg.p);
+    R2P_LAUNCH();
+    R2P_HIP(hipStreamSynchronize(s));
+    *nc = cnt;
+    return 0;
+}
+
+int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
+    r2p_jacobian *J = P->J;
+    const Phys &ph = J->m->ph;
+    int n = ph.n;
+    AmgLevel &L0 = P->lv[0];
+    // level 0 structure (static per model)
+    if (P->app_n != n) {
+        R2P_TRY(L0.rp.ensure(n + 1));
+        k_app_count<<<r2p_blocks(n, BS), BS, 0, s>>>(ph, L0.rp.p);
+        R2P_LAUNCH();
+        R2P_HIP(hipMemsetAsync(L0.rp.p + n, 0, sizeof(int), s));
+        int nnz = 0;
+        R2P_TRY(r2p_scan_int(L0.rp.p, L0.rp.p, n + 1, &nnz, P->iscratch, P->pin, s));
+        R2P_TRY(L0.col.ensure(nnz));
+        R2P_TRY(P->iscratch2.ensure(nnz));
+        k_app_cols<<<r2p_blocks(n, BS), BS, 0, s>>>(ph, L0.rp.p, L0.col.p, P->iscratch2.p);
+        R2P_LAUNCH();
+        L0.n = n;
+        L0.nnz = nnz;
+        P->app_n = n;
+    }
+    R2P_TRY(L0.val.ensure(L0.nnz));
+    k_app_vals<<<r2p_blocks(n, BS), BS, 0, s>>>(n, L0.rp.p, P->iscratch2.p, J->vp.p, L0.val.p);
+    R2P_LAUNCH();
+    int maxlev = std::min(std::max(P->o.max_levels, 1), 24);
+    int passes = std::max(P->o.agg_passes, 1);
+    int l = 0;
+    while (P->lv[l].n > P->o.max_coarse && l + 1 < maxlev) {
+        AmgLevel &A = P->lv[l];
+        AmgLevel &C = P->lv[l + 1];
+        R2P_TRY(A.agg.ensure(A.n));
+        k_iota<<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, A.agg.p);
+        R2P_LAUNCH();
+        // successive passes, each on the Galerkin product of the previous one
+        DBuf<int> crp[2], ccol[2];
+        DBuf<double> cval[2];
+        const int *rp = A.rp.p, *col = A.col.p;
+        const double *val = A.val.p;
+        int cn = A.n, nc = A.n, nnzc = 0, cnnz = A.nnz;
+        for (int p = 0; p < passes; p++) {
+            DBuf<int> a;
+            R2P_TRY(aggregate_pass(P, cn, rp, col, val, a, &nc, s));
+            bool last = p == passes - 1;
+            DBuf<int> &orp = last ? C.rp : crp[p & 1];
+            DBuf<int> &ocol = last ? C.col : ccol[p & 1];
+            DBuf<double> &oval = last ? C.val : cval[p & 1];
+            R2P_TRY(galerkin(P, cn, cnnz, rp, col, val, a.p, nc, orp, ocol, oval, &nnzc, s));
+            cnnz = nnzc;
+            k_compose<<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, a.p, A.agg.p);
+            R2P_LAUNCH();
+            R2P_HIP(hipStreamSynchronize(s));
+            rp = orp.p; col = ocol.p; val = oval.p;
+            cn = nc;
+        }
+        if (nc >= A.n) break;   // no coarsening progress
+        C.n = nc;
+        C.nnz = nnzc;
+        R2P_TRY(build_members(P, A.n, A.agg.p, nc, A.mptr, A.mem, s));
+        l++;
+    }
+    P->nlev = l + 1;
+    bool f32 = P->o.precision == R2P_FP32;
+    for (int k = 0; k < P->nlev; k++) {
+        AmgLevel &A = P->lv[k];
+        R2P_TRY(A.l1.ensure(A.n));
+        k_l1<<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, A.rp.p, A.val.p, A.l1.p);
+        R2P_LAUNCH();
+        if (f32) {
+            R2P_TRY(A.f32.val.ensure(A.nnz));
+            R2P_TRY(A.f32.l1.ensure(A.n));
+            R2P_TRY(A.bf.ensure(A.n));
+            R2P_TRY(A.xf.ensure(A.n));
+            R2P_TRY(A.xof.ensure(A.n));
+            k_castv<float><<<r2p_blocks(A.nnz, BS), BS, 0, s>>>(A.nnz, A.val.p, A.f32.val.p);
+            R2P_LAUNCH();
+            k_castv<float><<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, A.l1.p, A.f32.l1.p);
+            R2P_LAUNCH();
+        }
+        R2P_TRY(A.b.ensure(A.n));
+        R2P_TRY(A.x.ensure(A.n));
+        R2P_TRY(A.xo.ensure(A.n));
+    }
+    // coarsest level: dense LU and inverse (FP64)
+    AmgLevel &C = P->lv[P->nlev - 1];
+    int nc = C.n;
+    if (nc > 4096) { r2p_set_error("coarsest AMG level too large (%d rows)", nc); return R2P_EINVAL; }
+    P->ncoarse = nc;
+    R2P_TRY(P->lu.ensure((size_t)nc * nc));
+    R2P_TRY(P->cinv.ensure((size_t)nc * nc));
+    R2P_TRY(P->piv.ensure(nc));
+    R2P_TRY(P->status.ensure(4));
+    R2P_HIP(hipMemsetAsync(P->status.p + 1, 0, sizeof(int), s));
+    k_to_dense<<<r2p_blocks(nc, BS), BS, 0, s>>>(nc, C.rp.p, C.col.p, C.val.p, P->lu.p);
+    R2P_LAUNCH();
+    k_dense_lu_inv<<<1, 1024, 0, s>>>(nc, P->lu.p, P->piv.p, P->cinv.p, P->status.p + 1);
+    R2P_LAUNCH();
+    int *h = (int *)P->pin.p;
+    R2P_HIP(hipMemcpyAsync(h, P->status.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    R2P_HIP(hipStreamSynchronize(s));
+    if (*h) { r2p_set_error("coarsest AMG matrix is singular"); return R2P_ESINGULAR; }
+    return 0;
+}
+
+// --------------------------------------------------------------- V-cycle
+template <class T>
+struct DownArgs {
+    int n;
+    const int *rp, *col;
+    const T *val, *l1;
+    const T *b;                  // right-hand side of this level (or NULL: use f)
+    const double *f;             // level 0: Pi_r f read from the full vector
+    int fstride;
+    T *x;                        // pre-smoothed iterate of this level
+    T *r;                        // its residual
+};
+
+// Pre-smoothing from a zero guess (x = b / d) and the residual r = b - A x,
+// one thread per row.
+template <class T>
+__global__ void k_down(DownArgs<T> A) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    T bi = A.f ? (T)A.f[(long)A.fstride * i] : A.b[i];
+    A.x[i] = bi / A.l1[i];
+    T r = bi;
+    for (int z = A.rp[i]; z < A.rp[i + 1]; z++) {
+        int j = A.col[z];
+        T bj = A.f ? (T)A.f[(long)A.fstride * j] : A.b[j];
+        r -= A.val[z] * (bj / A.l1[j]);
+    }
+    A.r[i] = r;
+}
+
+// Restriction P^T r: each coarse row sums its fine members in ascending order.
+template <class T>
+__global__ void k_restrict(int nc, const int *mptr, const int *mem, const T *r, T *bc) {
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    T acc = (T)0;
+    for (int t = mptr[I]; t < mptr[I + 1]; t++) acc += r[mem[t]];
+    bc[I] = acc;
+}
+
+template <class T>
+struct UpArgs {
+    int n;
+    const int *rp, *col, *agg;
+    const T *val, *l1;
+    const T *b;
+    const double *f;
+    int fstride;
+    const T *x;                  // pre-smoothed iterate
+    const T *xc;                 // coarse correction
+    T *xo;                       // output (this level's result)
+    double *xod;                 // level 0: FP64 output
+};
+
+// Prolongation of the coarse correction and post-smoothing, one thread per
+// fine row: x' = x + P xc; x'' = x' + (b - A x') / d.
+template <class T>
+__global__ void k_up(UpArgs<T> A) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    T bi = A.f ? (T)A.f[(long)A.fstride * i] : A.b[i];
+    T r = bi;
+    for (int z = A.rp[i]; z < A.rp[i + 1]; z++) {
+        int j = A.col[z];
+        r -= A.val[z] * (A.x[j] + A.xc[A.agg[j]]);
+    }
+    T xi = A.x[i] + A.xc[A.agg[i]];
+    T v = xi + r / A.l1[i];
+    if (A.xod) A.xod[i] = (double)v;
+    else A.xo[i] = v;
+}
+
+template <class T>
+__global__ void k_coarse_solve(int n, const double *invT, const T *b, const double *f, int fstride,
+                               T *x, double *xd) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < n; c++) {
+        double bc = f ? f[(long)fstride * c] : (double)b[c];
+        s += invT[(long)c * n + i] * bc;
+    }
+    if (xd) xd[i] = s;
+    else x[i] = (T)s;
+}
+
+template <class T>
+static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStream_t s) {
+    int nl = P->nlev;
+    auto vals = [&](AmgLevel &A) -> const T * {
+        if constexpr (sizeof(T) == 4) return A.f32.val.p; else return (const T *)A.val.p;
+    };
+    auto l1s = [&](AmgLevel &A) -> const T * {
+        if constexpr (sizeof(T) == 4) return A.f32.l1.p; else return (const T *)A.l1.p;
+    };
+    auto vb = [&](AmgLevel &A) -> T * {
+        if constexpr (sizeof(T) == 4) return A.bf.p; else return (T *)A.b.p;
+    };
+    auto vx = [&](AmgLevel &A) -> T * {
+        if constexpr (sizeof(T) == 4) return A.xf.p; else return (T *)A.x.p;
+    };
+    auto vxo = [&](AmgLevel &A) -> T * {
+        if constexpr (sizeof(T) == 4) return A.xof.p; else return (T *)A.xo.p;
+    };
+    if (nl == 1) {
+        AmgLevel &C = P->lv[0];
+        k_coarse_solve<T><<<r2p_blocks(C.n, BS), BS, 0, s>>>(C.n, P->cinv.p, vb(C), f, fstride,
+                                                            vx(C), xp);
+        R2P_LAUNCH();
+        return 0;
+    }
+    for (int l = 0; l < nl - 1; l++) {
+        AmgLevel &A = P->lv[l];
+        AmgLevel &C = P->lv[l + 1];
+        // the level's output buffer holds its residual until the up sweep
+        DownArgs<T> D;
+        D.n = A.n; D.rp = A.rp.p; D.col = A.col.p;
+        D.val = vals(A); D.l1 = l1s(A);
+        D.b = l == 0 ? nullptr : vb(A);
+        D.f = l == 0 ? f : nullptr;
+        D.fstride = fstride;
+        D.x = vx(A); D.r = vxo(A);
+        k_down<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(D);
+        R2P_LAUNCH();
+        k_restrict<T><<<r2p_blocks(C.n, BS), BS, 0, s>>>(C.n, A.mptr.p, A.mem.p, vxo(A), vb(C));
+        R2P_LAUNCH();
+    }
+    AmgLevel &Cst = P->lv[nl - 1];
+    k_coarse_solve<T><<<r2p_blocks(Cst.n, BS), BS, 0, s>>>(Cst.n, P->cinv.p, vb(Cst), nullptr, 1,
+                                                          vxo(Cst), nullptr);
+    R2P_LAUNCH();
+    for (int l = nl - 2; l >= 0; l--) {
+        AmgLevel &A = P->lv[l];
+        AmgLevel &C = P->lv[l + 1];
+        UpArgs<T> U;
+        U.n = A.n; U.rp = A.rp.p; U.col = A.col.p; U.agg = A.agg.p; U.val = vals(A); U.l1 = l1s(A);
+        U.b = l == 0 ? nullptr : vb(A);
+        U.f = l == 0 ? f : nullptr;
+        U.fstride = fstride;
+        U.x = vx(A); U.xc = vxo(C);
+        U.xo = vxo(A);
+        U.xod = l == 0 ? xp : nullptr;
+        k_up<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(U);
+        R2P_LAUNCH();
+    }
+    return 0;
+}
+
+int r2p_amg_cycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStream_t s) {
+    if (P->o.precision == R2P_FP32) return vcycle<float>(P, f, fstride, xp, s);
+    return vcycle<double>(P, f, fstride, xp, s);
+}
+
+extern "C" int r2p_amg_info(r2p_cpr *P, int level, int *nlev, int *n, int *nnz) {
+    if (!P || !P->ready) { r2p_set_error("CPR not set up"); return R2P_ESTATE; }
+    if (nlev) *nlev = P->nlev;
+    if (level >= 0 && level < P->nlev) {
+        if (n) *n = P->lv[level].n;
+        if (nnz) *nnz = P->lv[level].nnz;
+    }
+    return 0;
+}
+
+extern "C" int r2p_amg_export_level(r2p_cpr *P, int level, int *rp, int *col, double *val,
+                                    double *l1, int *agg, void *stream) {
+    if (!P || !P->ready) { r2p_set_error("CPR not set up"); return R2P_ESTATE; }
+    if (level < 0 || level >= P->nlev) { r2p_set_error("bad level"); return R2P_EINVAL; }
+    R2P_HIP(hipStreamSynchronize((hipStream_t)stream));
+    AmgLevel &A = P->lv[level];
+    if (rp) R2P_HIP(hipMemcpy(rp, A.rp.p, sizeof(int) * (A.n + 1), hipMemcpyDeviceToHost));
+    if (col) R2P_HIP(hipMemcpy(col, A.col.p, sizeof(int) * A.nnz, hipMemcpyDeviceToHost));
+    if (val) R2P_HIP(hipMemcpy(val, A.val.p, sizeof(double) * A.nnz, hipMemcpyDeviceToHost));
+    if (l1) R2P_HIP(hipMemcpy(l1, A.l1.p, sizeof(double) * A.n, hipMemcpyDeviceToHost));
+    if (agg && level < P->nlev - 1)
+        R2P_HIP(hipMemcpy(agg, A.agg.p, sizeof(int) * A.n, hipMemcpyDeviceToHost));
+    return 0;
+}

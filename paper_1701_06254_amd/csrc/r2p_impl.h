@@ -1,0 +1,244 @@
+// Internal definitions of the r2p device library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/r2p.h"
+
+// ------------------------------------------------------------------ errors
+void r2p_set_error(const char *fmt, ...);
+int r2p_hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define R2P_HIP(expr)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess) return r2p_hip_fail(e_, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+#define R2P_TRY(expr)                                                          \
+    do {                                                                       \
+        int rc_ = (expr);                                                      \
+        if (rc_ < 0) return rc_;                                               \
+    } while (0)
+
+#define R2P_LAUNCH()  R2P_HIP(hipGetLastError())
+
+// ------------------------------------------------------- device allocations
+// Grow-only device buffer; contents are not preserved on growth.
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t nbytes);
+    void release();
+    ~DevMem() { release(); }
+};
+
+template <class T>
+struct DBuf {
+    DevMem mem;
+    T *p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t n) {
+        size_t need = n > 0 ? n : 1;
+        if (need <= cap && p) return 0;
+        int rc = mem.ensure(need * sizeof(T));
+        if (rc) return rc;
+        p = (T *)mem.p;
+        cap = need;
+        return 0;
+    }
+    void release() { mem.release(); p = nullptr; cap = 0; }
+};
+
+// Pinned host staging for small read-backs.
+struct HostPinned {
+    void *p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t nbytes);
+    ~HostPinned();
+};
+
+// --------------------------------------------------------------- physics
+struct Phys {
+    int nx, ny, nz, n, nw, nperf;
+    double dx, dy, dz, top;
+    double beta, alpha, rho_o, rho_w, p_ref, z_ref, c_o, c_w, c_r, mu_o, mu_w, grav;
+};
+
+struct r2p_model {
+    int dev = 0;
+    Phys ph{};
+    // device arrays
+    DBuf<double> kx, ky, kz, phi;      // n
+    DBuf<double> tx, ty, tz;           // n: geometric transmissibility to the +x/+y/+z neighbour
+    DBuf<int> cell_perf;               // n: perforation index or -1
+    DBuf<int> perf_cell, perf_well;    // nperf
+    DBuf<double> perf_wi;              // nperf
+    DBuf<int> w_ptr, w_kind, w_ctrl;   // nw(+1)
+    DBuf<double> w_target, w_zb, w_rw, w_skin;
+    // host copies of the well description
+    std::vector<int> h_w_ptr, h_w_cell, h_w_kind, h_w_ctrl;
+    std::vector<double> h_w_target;
+    // reduction scratch
+    DBuf<unsigned long long> red;
+    HostPinned pin;
+};
+
+// Jacobian in a 7-slot stencil layout: slot 0 = the cell itself, 1/2 = -x/+x,
+// 3/4 = -y/+y, 5/6 = -z/+z.  Columns are implied by the grid; a slot whose
+// neighbour does not exist holds a zero block and a clamped column.  Each
+// block [[a00 a01] [a10 a11]] is split into a pressure-column plane
+// vp = (a00, a10) and a saturation-column plane vs = (a01, a11), slot-major:
+// vp[slot*n + c].
+struct r2p_jacobian {
+    r2p_model *m = nullptr;
+    DBuf<double2> vp, vs;   // 7n
+    DBuf<double2> cw;       // nperf: d(cell oil, water eq)/d p_b
+    DBuf<double2> wc;       // nperf: d(well eq)/d(p_cell, s_cell)
+    DBuf<double> wd;        // nw: d(well eq)/d p_b
+    DBuf<double> phi_o;     // n: oil potential at the assembled state
+    DBuf<double4> dec;      // n: decoupling row operator D_i^-1 (row-major)
+    int state = 0;          // 0 empty, 1 assembled, 2 decoupled
+    int dec_kind = 0;
+};
+
+__host__ __device__ inline int slot_offset(int s, int nx, int nxy) {
+    switch (s) {
+    case 1: return -1;
+    case 2: return 1;
+    case 3: return -nx;
+    case 4: return nx;
+    case 5: return -nxy;
+    case 6: return nxy;
+    default: return 0;
+    }
+}
+
+// ------------------------------------------------------------------ RAS
+// Block ILU(0) factors of every overlapped subdomain, rows stored in level
+// order (rows of one level are independent).  Per local row p (global
+// position index into the concatenation of all subdomains):
+//   glob[p]    global block row;  owned[p] restricted-scatter flag
+//   eptr[p]..eptr[p+1]  off-diagonal factor blocks, the first nl[p] are L
+//                       (predecessors, ascending local order), then U
+//   ecol[e]    local position of the block's column row
+//   dinv[p]    inverse of U's diagonal block
+template <class T>
+struct RasFactors {
+    DBuf<T> eval;     // 4 per block
+    DBuf<T> dinv;     // 4 per row
+};
+
+struct RasStatic {
+    // membership and local adjacency (depend on model + px, py, overlap only)
+    int ns = 0, px = 0, py = 0, overlap = -1;
+    int mtot = 0;                         // total local rows over subdomains
+    std::vector<int> h_off;               // ns+1 local row offsets per subdomain
+    DBuf<int> glob_nat;                   // mtot: global row of local row (natural order)
+    DBuf<unsigned char> owned_nat;        // mtot
+    DBuf<int> aptr, adj, asrc;            // local adjacency: neighbour local index, block source
+    int nadj = 0;
+    DBuf<int> dsrc;                       // mtot: source of the diagonal block
+    DBuf<int> sub_of;                     // mtot: subdomain of local row
+};
+
+struct RasDyn {
+    int maxlev = 0;
+    std::vector<int> h_lptr;              // per subdomain level offsets (flattened)
+    std::vector<int> h_nlev;              // levels per subdomain
+    std::vector<int> h_lbase;             // index into h_lptr per subdomain
+    DBuf<int> lev;                        // mtot: level of local row (natural)
+    DBuf<int> pos;                        // mtot: position of local row in level order
+    DBuf<int> perm;                       // mtot: local row (natural) at position
+    DBuf<int> glob;                       // mtot: global row at position
+    DBuf<unsigned char> owned;            // mtot
+    DBuf<int> eptr;                       // mtot+1
+    DBuf<int> nl;                         // mtot
+    DBuf<int> ecol;                       // nadj
+    DBuf<int> esrc;                       // nadj: block source per factor entry (setup only)
+    DBuf<int> lptr_dev;                   // flattened level pointers (positions)
+    DBuf<int> sub_lbase;                  // ns: base into lptr_dev
+    DBuf<int> sub_nlev;                   // ns
+    DBuf<int> counters;                   // scratch
+    RasFactors<double> f64;
+    RasFactors<float> f32;
+};
+
+// ------------------------------------------------------------------ AMG
+template <class T>
+struct AmgLevelT {
+    DBuf<T> val;
+    DBuf<T> l1;
+};
+
+struct AmgLevel {
+    int n = 0, nnz = 0;
+    DBuf<int> rp, col;
+    DBuf<double> val, l1;
+    DBuf<int> agg;           // n: row of the next level
+    DBuf<int> mptr, mem;     // next level's member lists (n_next+1, n)
+    AmgLevelT<float> f32;
+    DBuf<double> b, x, xo;   // work vectors (fp64)
+    DBuf<float> bf, xf, xof; // work vectors (fp32)
+};
+
+struct r2p_cpr {
+    r2p_cpr_opts o{};
+    r2p_jacobian *J = nullptr;
+    int ready = 0;
+    RasStatic rs;
+    RasDyn rd;
+    int nlev = 0;
+    AmgLevel lv[24];
+    int ncoarse = 0;
+    DBuf<double> cinv;       // coarsest inverse, row-major
+    DBuf<float> cinvf;
+    DBuf<double> lu;         // coarsest dense LU scratch
+    DBuf<int> piv;
+    DBuf<int> status;        // device status flags
+    // level-0 structure cache
+    int app_n = -1;
+    // work vectors
+    DBuf<double> t_r, t_y, t_xp, t_ras;
+    DBuf<float> t_rasf;
+    DBuf<int> iscratch;
+    DBuf<int> iscratch2;
+    DBuf<double> dscratch;
+    HostPinned pin;
+};
+
+// ------------------------------------------------------------ utilities
+// Exclusive scan of n ints (in may equal out); returns the total if
+// total_host != NULL (synchronises the stream).
+// Stable radix sort of n (key, value) pairs on the low key_bits bits of the
+// key, in place (ktmp/vtmp: scratch of n each).
+int r2p_sort_pairs(unsigned *key, unsigned *val, unsigned *ktmp, unsigned *vtmp, int n,
+                   int key_bits, DBuf<int> &hist, DBuf<int> &tmp, HostPinned &pin, hipStream_t s);
+inline int r2p_bits_for(long n) {
+    int b = 1;
+    while ((1L << b) < n) b++;
+    return b;
+}
+int r2p_scan_int(const int *in, int *out, int n, int *total_host, DBuf<int> &tmp,
+                 HostPinned &pin, hipStream_t s);
+
+inline int r2p_blocks(long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// Internal entry points shared between translation units.
+int r2p_cpr_apply_impl(r2p_cpr *P, const double *f, double *z, hipStream_t s);
+int r2p_spmv_impl(r2p_jacobian *J, const double *x, double *y, const double *f, hipStream_t s);
+int r2p_decouple_rhs(r2p_jacobian *J, const double *b, double *bd, hipStream_t s);
+int r2p_ras_setup(r2p_cpr *P, hipStream_t s);
+int r2p_amg_setup(r2p_cpr *P, hipStream_t s);
+int r2p_ras_solve(r2p_cpr *P, const double *r, double *out, const double *xp, int accumulate,
+                  hipStream_t s);
+int r2p_amg_cycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStream_t s);
+int r2p_pcol_residual(r2p_jacobian *J, const double *f, const double *xp, double *r,
+                      hipStream_t s);
+int r2p_decouple_jacobian(r2p_jacobian *J, int kind, hipStream_t s);
+int r2p_newton_update(r2p_model *m, const double *y, double *x, double ds_max, hipStream_t s);

@@ -1,0 +1,516 @@
+// CPR preconditioner application, flexible GMRES and Newton's method.
+//
+// Paper sections: "Multi-stage preconditioner" (Eq 34-35 and Algorithm 2;
+// the two-stage form is Algorithm 2 entered at its third step with x = 0),
+// restarted GMRES as the Krylov solver ("Numerical experiments", Examples
+// 4-5), and "Nonlinear methods" (Algorithm 1, forcing terms of Eq 26).
+//
+// Device design.  The Arnoldi process is classical Gram-Schmidt: one pass
+// computes every projection h = V^T w and w.w together (fused multi-dot with
+// a fixed-order two-stage reduction), a second pass forms the new basis
+// vector (w - V h) / ||w - V h|| with the norm from Pythagoras.  When the
+// projection removes more than half of ||w||^2 the pass is repeated once
+// (selective reorthogonalisation, Daniel-Gragg-Kaufman-Stewart criterion).
+// The (m+1) x m Hessenberg matrix and its Givens rotations live on the host;
+// each iteration reads back one column.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "r2p_impl.h"
+
+int r2p_decouple_jacobian(r2p_jacobian *J, int kind, hipStream_t s);
+int r2p_newton_update(r2p_model *m, const double *y, double *x, double ds_max, hipStream_t s);
+
+constexpr int BS = 256;
+constexpr int EPT = 8;                  // elements per thread in the dot kernels
+constexpr int TILE = BS * EPT;
+constexpr int MAXV = 65;                // basis vectors + 1 (w.w)
+
+// ----------------------------------------------------------- multi-dot
+// h[k] = V_k . w (k < nv) and h[nv] = w . w.  Per-workgroup partial sums,
+// then the last workgroup to finish (ticket) adds the partials in block
+// order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(BS) void k_mdot(const double *V, long ld, int nv, const double *w,
+                                             long N, double *part, double *h, unsigned *ticket) {
+    __shared__ double red[BS / 64][MAXV];
+    __shared__ bool last;
+    long base = (long)blockIdx.x * TILE + threadIdx.x;
+    double wv[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; e++) {
+        long i = base + (long)e * BS;
+        wv[e] = i < N ? w[i] : 0.0;
+    }
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = 0; k <= nv; k++) {
+        double acc = 0.0;
+        if (k < nv) {
+            const double *vk = V + (long)k * ld;
+#pragma unroll
+            for (int e = 0; e < EPT; e++) {
+                long i = base + (long)e * BS;
+                acc += (i < N ? vk[i] : 0.0) * wv[e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < EPT; e++) acc += wv[e] * wv[e];
+        }
+        for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+        if (lane == 0) red[wid][k] = acc;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k <= nv; k += BS) {
+        double s = 0.0;
+        for (int q = 0; q < BS / 64; q++) s += red[q][k];
+        part[(long)blockIdx.x * MAXV + k] = s;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    __shared__ double sred[BS];
+    int nb = gridDim.x;
+    for (int k = 0; k <= nv; k++) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += BS)
+            s += __hip_atomic_load(&part[(long)b * MAXV + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sred[threadIdx.x] = s;
+        __syncthreads();
+        for (int st = BS / 2; st > 0; st >>= 1) {
+            if (threadIdx.x < st) sred[threadIdx.x] += sred[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) h[k] = sred[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *ticket = 0u;
+}
+
+// out = (w - sum_k h[k] V_k) * scale   (out may alias w)
+__global__ __launch_bounds__(BS) void k_mupdate(const double *V, long ld, int nv, const double *h,
+                                                const double *w, long N, double scale,
+                                                double *out) {
+    __shared__ double hs[MAXV];
+    for (int k = threadIdx.x; k < nv; k += BS) hs[k] = h[k];
+    __syncthreads();
+    long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i >= N) return;
+    double t = w[i];
+    for (int k = 0; k < nv; k++) t -= hs[k] * V[(long)k * ld + i];
+    out[i] = t * scale;
+}
+
+struct Coef {
+    double c[64];
+};
+
+// x += sum_k y_k Z_k
+__global__ __launch_bounds__(BS) void k_maxpy(const double *Z, long ld, int nv, Coef y, long N,
+                                              double *x) {
+    long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i >= N) return;
+    double t = x[i];
+    for (int k = 0; k < nv; k++) t += y.c[k] * Z[(long)k * ld + i];
+    x[i] = t;
+}
+
+// r_orig = D (r_dec) per cell row: the residual of the undecoupled system.
+__global__ void k_undecouple(int n, long N, const double4 *dec, const double *rd, double *r) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) {
+        double4 M = dec[i];
+        double det = M.x * M.w - M.y * M.z;
+        double a = rd[2 * i], b = rd[2 * i + 1];
+        r[2 * i] = (M.w * a - M.y * b) / det;
+        r[2 * i + 1] = (-M.z * a + M.x * b) / det;
+    } else if (2 * i < N) {
+        r[2 * i] = rd[2 * i];
+        r[2 * i + 1] = rd[2 * i + 1];
+    }
+}
+
+struct Krylov {
+    DBuf<double> V, Z, part, h, r, bd, w;
+    DBuf<unsigned> ticket;
+    HostPinned pin;
+    long N = 0;
+    int m = 0;
+};
+
+static Krylov &krylov_for(r2p_cpr *P);
+
+static int mdot(Krylov &K, const double *V, int nv, const double *w, long N, hipStream_t s,
+                double *hhost) {
+    int nb = r2p_blocks(N, TILE);
+    R2P_TRY(K.part.ensure((size_t)nb * MAXV));
+    k_mdot<<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p, K.h.p, K.ticket.p);
+    R2P_LAUNCH();
+    if (hhost) {
+        R2P_HIP(hipMemcpyAsync(K.pin.p, K.h.p, sizeof(double) * (nv + 1), hipMemcpyDeviceToHost, s));
+        R2P_HIP(hipStreamSynchronize(s));
+        memcpy(hhost, K.pin.p, sizeof(double) * (nv + 1));
+    }
+    return 0;
+}
+
+// ------------------------------------------------------------------ CPR
+int r2p_cpr_apply_impl(r2p_cpr *P, const double *f, double *z, hipStream_t s) {
+    r2p_jacobian *J = P->J;
+    if (P->o.form == R2P_CPR_FPF) {
+        // Algorithm 2: x = R^-1 f; r = f - A x; x += Pi_p M^-1 Pi_r r;
+        // r = f - A x; x += R^-1 r
+        R2P_TRY(r2p_ras_solve(P, f, z, nullptr, 0, s));
+        R2P_TRY(r2p_spmv_impl(J, z, P->t_r.p, f, s));
+        R2P_TRY(r2p_amg_cycle(P, P->t_r.p, 2, P->t_xp.p, s));
+        R2P_TRY(r2p_pcol_residual(J, P->t_r.p, P->t_xp.p, P->t_y.p, s));
+        R2P_TRY(r2p_ras_solve(P, P->t_y.p, z, P->t_xp.p, 1, s));
+    } else {
+        // x = Pi_p M^-1 Pi_r f; r = f - A x; x += R^-1 r
+        R2P_TRY(r2p_amg_cycle(P, f, 2, P->t_xp.p, s));
+        R2P_TRY(r2p_pcol_residual(J, f, P->t_xp.p, P->t_r.p, s));
+        R2P_TRY(r2p_ras_solve(P, P->t_r.p, z, P->t_xp.p, 0, s));
+    }
+    return 0;
+}
+
+extern "C" int r2p_cpr_create(r2p_cpr **out) {
+    if (!out) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
+    *out = new r2p_cpr();
+    return 0;
+}
+
+extern "C" int r2p_cpr_destroy(r2p_cpr *P) {
+    delete P;
+    return 0;
+}
+
+static int check_opts(const r2p_cpr_opts *o) {
+    if (o->decouple < 0 || o->decouple > 2 || o->order < 0 || o->order > 1 || o->form < 0 ||
+        o->form > 1 || o->px < 1 || o->py < 1 || o->px * o->py > 64 || o->overlap < 0 ||
+        o->overlap > 8 || !(o->theta >= 0) || o->max_coarse < 1 || o->max_coarse > 2048 ||
+        o->max_levels < 1 || o->match_rounds < 1 || o->agg_passes < 1 || o->agg_passes > 4 ||
+        o->precision < 0 || o->precision > 1) {
+        r2p_set_error("invalid CPR options");
+        return R2P_EINVAL;
+    }
+    return 0;
+}
+
+extern "C" int r2p_setup_cpr(r2p_jacobian *J, const r2p_cpr_opts *o, r2p_cpr *P, void *stream) {
+    if (!J || !o || !P) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
+    R2P_TRY(check_opts(o));
+    if (J->state != 1) { r2p_set_error("Jacobian not assembled since its last set-up"); return R2P_ESTATE; }
+    hipStream_t s = (hipStream_t)stream;
+    if (P->J && (P->J->m != J->m || P->o.px != o->px || P->o.py != o->py || P->o.overlap != o->overlap))
+        P->rs.ns = 0;   // membership must be rebuilt
+    if (P->J && P->J->m != J->m) P->app_n = -1;
+    P->ready = 0;
+    P->J = J;
+    P->o = *o;
+    const Phys &ph = J->m->ph;
+    long N = 2L * (ph.n + ph.nw);
+    R2P_TRY(P->t_r.ensure(N));
+    R2P_TRY(P->t_y.ensure(N));
+    R2P_TRY(P->t_xp.ensure(ph.n));
+    R2P_TRY(r2p_decouple_jacobian(J, o->decouple, s));
+    R2P_TRY(r2p_ras_setup(P, s));
+    R2P_TRY(r2p_amg_setup(P, s));
+    P->ready = 1;
+    return 0;
+}
+
+extern "C" int r2p_cpr_apply(r2p_cpr *P, const double *f, double *z, void *stream) {
+    if (!P || !f || !z) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
+    if (!P->ready) { r2p_set_error("CPR not set up"); return R2P_ESTATE; }
+    return r2p_cpr_apply_impl(P, f, z, (hipStream_t)stream);
+}
+
+extern "C" int r2p_amg_vcycle(r2p_cpr *P, const double *f_p, double *x_p, void *stream) {
+    if (!P || !f_p || !x_p) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
+    if (!P->ready) { r2p_set_error("CPR not set up"); return R2P_ESTATE; }
+    return r2p_amg_cycle(P, f_p, 1, x_p, (hipStream_t)stream);
+}
+
+extern "C" int r2p_ras_apply(r2p_cpr *P, const double *r, double *y, void *stream) {
+    if (!P || !r || !y) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
+    if (!P->ready) { r2p_set_error("CPR not set up"); return R2P_ESTATE; }
+    return r2p_ras_solve(P, r, y, nullptr, 0, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------- FGMRES
+static Krylov &krylov_for(r2p_cpr *P) {
+    static thread_local Krylov *K = nullptr;
+    (void)P;
+    if (!K) K = new Krylov();
+    return *K;
+}
+
+extern "C" int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y,
+                         const r2p_solve_opts *o, r2p_solve_info *info, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!J || !P || !b || !y || !o) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
+    if (!P->ready || P->J != J || J->state != 2) { r2p_set_error("CPR not set up for this Jacobian"); return R2P_ESTATE; }
+    if (o->restart < 1 || o->restart > 64 || o->maxit < 1 || !(o->rtol > 0)) {
+        r2p_set_error("invalid solve options");
+        return R2P_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const Phys &ph = J->m->ph;
+    long N = 2L * (ph.n + ph.nw);
+    int m = o->restart;
+    Krylov &K = krylov_for(P);
+    R2P_TRY(K.V.ensure((size_t)(m + 1) * N));
+    R2P_TRY(K.Z.ensure((size_t)m * N));
+    R2P_TRY(K.r.ensure(N));
+    R2P_TRY(K.bd.ensure(N));
+    R2P_TRY(K.h.ensure(MAXV));
+    R2P_TRY(K.pin.ensure(sizeof(double) * MAXV * 2));
+    if (!K.ticket.p) {
+        R2P_TRY(K.ticket.ensure(1));
+        R2P_HIP(hipMemsetAsync(K.ticket.p, 0, sizeof(unsigned), s));
+    }
+    R2P_TRY(r2p_decouple_rhs(J, b, K.bd.p, s));
+    double hb[MAXV];
+    R2P_TRY(mdot(K, nullptr, 0, K.bd.p, N, s, hb));
+    double bnorm = sqrt(hb[0]);
+    R2P_HIP(hipMemsetAsync(y, 0, sizeof(double) * N, s));
+    r2p_solve_info inf{};
+    int status = R2P_NOT_CONVERGED;
+    if (!(bnorm == bnorm) || std::isinf(bnorm)) { r2p_set_error("non-finite right-hand side"); return R2P_ENAN; }
+    if (bnorm == 0.0) {
+        status = 0;
+        inf.relres = 0.0;
+    } else {
+        std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m);
+        R2P_HIP(hipMemcpyAsync(K.r.p, K.bd.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        double beta = bnorm;
+        int total = 0;
+        int nblk = r2p_blocks(N, BS);
+        while (total < o->maxit) {
+            k_mupdate<<<nblk, BS, 0, s>>>(nullptr, N, 0, K.h.p, K.r.p, N, 1.0 / beta, K.V.p);
+            R2P_LAUNCH();
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int k = 0;
+            bool stop = false;
+            for (int j = 0; j < m && total < o->maxit; j++) {
+                double *vj = K.V.p + (size_t)j * N, *zj = K.Z.p + (size_t)j * N;
+                double *w = K.V.p + (size_t)(j + 1) * N;
+                R2P_TRY(r2p_cpr_apply_impl(P, vj, zj, s));
+                R2P_TRY(r2p_spmv_impl(J, zj, w, nullptr, s));
+                double hh[MAXV];
+                R2P_TRY(mdot(K, K.V.p, j + 1, w, N, s, hh));
+                double ww = hh[j + 1], hs = 0.0;
+                for (int i = 0; i <= j; i++) hs += hh[i] * hh[i];
+                double wn2 = ww - hs;
+                double hn;
+                if (wn2 > 0.49 * ww) {
+                    hn = sqrt(wn2);
+                    k_mupdate<<<nblk, BS, 0, s>>>(K.V.p, N, j + 1, K.h.p, w, N, 1.0 / hn, w);
+                    R2P_LAUNCH();
+                } else {
+                    // second Gram-Schmidt pass
+                    inf.reorth++;
+                    k_mupdate<<<nblk, BS, 0, s>>>(K.V.p, N, j + 1, K.h.p, w, N, 1.0, w);
+                    R2P_LAUNCH();
+                    double h2[MAXV];
+                    R2P_TRY(mdot(K, K.V.p, j + 1, w, N, s, h2));
+                    double hs2 = 0.0;
+                    for (int i = 0; i <= j; i++) { hh[i] += h2[i]; hs2 += h2[i] * h2[i]; }
+                    double wn = h2[j + 1] - hs2;
+                    hn = wn > 0.0 ? sqrt(wn) : 0.0;
+                    if (hn > 0.0) {
+                        k_mupdate<<<nblk, BS, 0, s>>>(K.V.p, N, j + 1, K.h.p, w, N, 1.0 / hn, w);
+                        R2P_LAUNCH();
+                    }
+                }
+                for (int i = 0; i <= j; i++) H[(size_t)i * m + j] = hh[i];
+                H[(size_t)(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; i++) {
+                    double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+                    H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                    H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+                }
+                double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+                double den = sqrt(a * a + c * c);
+                total++;
+                if (den == 0.0 || den != den) { status = R2P_BREAKDOWN; stop = true; break; }
+                cs[j] = a / den;
+                sn[j] = c / den;
+                H[(size_t)j * m + j] = den;
+                H[(size_t)(j + 1) * m + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                k = j + 1;
+                if (fabs(g[j + 1]) <= o->rtol * bnorm || hn == 0.0) break;
+            }
+            if (k > 0) {
+                for (int i = k - 1; i >= 0; i--) {
+                    double sum = g[i];
+                    for (int t = i + 1; t < k; t++) sum -= H[(size_t)i * m + t] * yv[t];
+                    yv[i] = sum / H[(size_t)i * m + i];
+                }
+                Coef cf;
+                for (int i = 0; i < k; i++) cf.c[i] = yv[i];
+                k_maxpy<<<nblk, BS, 0, s>>>(K.Z.p, N, k, cf, N, y);
+                R2P_LAUNCH();
+            }
+            R2P_TRY(r2p_spmv_impl(J, y, K.r.p, K.bd.p, s));
+            double rr[2];
+            R2P_TRY(mdot(K, nullptr, 0, K.r.p, N, s, rr));
+            beta = sqrt(rr[0]);
+            inf.relres = beta / bnorm;
+            if (beta <= o->rtol * bnorm) { status = 0; break; }
+            if (stop || beta == 0.0 || beta != beta) break;
+        }
+        inf.iterations = total;
+    }
+    inf.status = status;
+    inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return status;
+}
+
+// ---------------------------------------------------------------- Newton
+extern "C" void r2p_default_newton_opts(r2p_newton_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->max_newton = 20;
+    o->tol = 1e-8;
+    o->forcing = R2P_FORCING_FIXED;
+    o->ds_max = 0.2;
+    o->cpr.decouple = R2P_DEC_QI;
+    o->cpr.order = R2P_ORDER_POTENTIAL;
+    o->cpr.form = R2P_CPR_TWO_STAGE;
+    o->cpr.px = 4;
+    o->cpr.py = 4;
+    o->cpr.overlap = 1;
+    o->cpr.theta = 0.25;
+    o->cpr.max_coarse = 500;
+    o->cpr.max_levels = 20;
+    o->cpr.match_rounds = 4;
+    o->cpr.agg_passes = 2;
+    o->cpr.precision = R2P_FP64;
+    o->lin.restart = 30;
+    o->lin.maxit = 300;
+    o->lin.rtol = 1e-8;
+}
+
+struct NewtonWork {
+    r2p_model *m = nullptr;
+    r2p_jacobian *J = nullptr;
+    r2p_cpr *P = nullptr;
+    DBuf<double> xold, xk, b, y, t;
+    ~NewtonWork() {
+        if (J) r2p_jacobian_destroy(J);
+        if (P) r2p_cpr_destroy(P);
+    }
+};
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+extern "C" int r2p_newton_step(r2p_model *m, double *x, double dt, const double *x_guess,
+                               const r2p_newton_opts *o, r2p_newton_info *info, void *stream) {
+    double T0 = now_ms();
+    if (!m || !x || !o) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
+    if (!(dt > 0) || o->max_newton < 1 || o->max_newton >= R2P_HIST || !(o->tol > 0)) {
+        r2p_set_error("invalid Newton options");
+        return R2P_EINVAL;
+    }
+    R2P_TRY(check_opts(&o->cpr));
+    hipStream_t s = (hipStream_t)stream;
+    static thread_local NewtonWork *W = nullptr;
+    if (!W || W->m != m) {
+        delete W;
+        W = new NewtonWork();
+        W->m = m;
+        R2P_TRY(r2p_jacobian_create(m, &W->J));
+        R2P_TRY(r2p_cpr_create(&W->P));
+    }
+    long N = 2L * (m->ph.n + m->ph.nw);
+    R2P_TRY(W->xold.ensure(N));
+    R2P_TRY(W->xk.ensure(N));
+    R2P_TRY(W->b.ensure(N));
+    R2P_TRY(W->y.ensure(N));
+    R2P_TRY(W->t.ensure(N));
+    r2p_newton_info inf{};
+    R2P_HIP(hipMemcpyAsync(W->xold.p, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    R2P_HIP(hipMemcpyAsync(W->xk.p, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    Krylov &K = krylov_for(W->P);
+    R2P_TRY(K.h.ensure(MAXV));
+    R2P_TRY(K.pin.ensure(sizeof(double) * MAXV * 2));
+    if (!K.ticket.p) {
+        R2P_TRY(K.ticket.ensure(1));
+        R2P_HIP(hipMemsetAsync(K.ticket.p, 0, sizeof(unsigned), s));
+    }
+    if (x_guess) {
+        double ng = 0.0, n0 = 0.0;
+        R2P_TRY(r2p_assemble_jacobian(m, x_guess, W->xold.p, dt, W->J, W->b.p, stream));
+        int rc = r2p_residual_norm(m, W->b.p, dt, &ng, stream);
+        R2P_TRY(r2p_assemble_jacobian(m, x, W->xold.p, dt, W->J, W->b.p, stream));
+        R2P_TRY(r2p_residual_norm(m, W->b.p, dt, &n0, stream));
+        if (rc == 0 && ng < n0) {
+            R2P_HIP(hipMemcpyAsync(W->xk.p, x_guess, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+            inf.used_guess = 1;
+        }
+    }
+    int status = R2P_NOT_CONVERGED;
+    double eta = 0.1, prev_fn = 0.0, prev_rn = 0.0;
+    for (int it = 0; it <= o->max_newton; it++) {
+        double ta = now_ms();
+        R2P_TRY(r2p_assemble_jacobian(m, W->xk.p, W->xold.p, dt, W->J, W->b.p, stream));
+        double sn = 0.0;
+        int rc = r2p_residual_norm(m, W->b.p, dt, &sn, stream);
+        inf.ms_assemble += now_ms() - ta;
+        inf.res_hist[it] = sn;
+        if (rc == R2P_ENAN) break;
+        R2P_TRY(rc);
+        if (sn <= o->tol) { status = 0; break; }
+        if (it == o->max_newton) break;
+        double hb[2];
+        R2P_TRY(mdot(K, nullptr, 0, W->b.p, N, s, hb));
+        double fn = sqrt(hb[0]);
+        if (o->forcing == R2P_FORCING_EW && it > 0) {
+            eta = fabs(fn - prev_rn) / prev_fn;
+            eta = eta < 0.01 ? 0.01 : (eta > 0.1 ? 0.1 : eta);
+        }
+        double ts = now_ms();
+        rc = r2p_setup_cpr(W->J, &o->cpr, W->P, stream);
+        inf.ms_setup += now_ms() - ts;
+        if (rc) return rc;
+        r2p_solve_opts lo = o->lin;
+        if (o->forcing == R2P_FORCING_EW) lo.rtol = eta;
+        r2p_solve_info si{};
+        double tl = now_ms();
+        rc = r2p_solve(W->J, W->P, W->b.p, W->y.p, &lo, &si, stream);
+        inf.ms_solve += now_ms() - tl;
+        inf.linear_its += si.iterations;
+        if (rc < 0) return rc;
+        if (rc != 0 && o->forcing == R2P_FORCING_FIXED) break;
+        if (o->forcing == R2P_FORCING_EW) {
+            // ||b - J y|| of the undecoupled system (Eq 27)
+            R2P_TRY(r2p_spmv_impl(W->J, W->y.p, W->t.p, K.bd.p, s));
+            k_undecouple<<<r2p_blocks(m->ph.n + m->ph.nw, BS), BS, 0, s>>>(m->ph.n, N, W->J->dec.p, W->t.p, W->t.p);
+            R2P_LAUNCH();
+            double hr[2];
+            R2P_TRY(mdot(K, nullptr, 0, W->t.p, N, s, hr));
+            prev_rn = sqrt(hr[0]);
+            prev_fn = fn;
+        }
+        R2P_TRY(r2p_newton_update(m, W->y.p, W->xk.p, o->ds_max, s));
+        inf.newton_its = it + 1;
+    }
+    if (status == 0)
+        R2P_HIP(hipMemcpyAsync(x, W->xk.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    R2P_HIP(hipStreamSynchronize(s));
+    inf.status = status;
+    inf.ms_total = now_ms() - T0;
+    if (info) *info = inf;
+    return status;
+}

@@ -1,0 +1,258 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Every input is seeded and synthetic; every expected value comes from the
+oracle.  Tolerances: assembly, decoupling and factor blocks to 1e-12
+relative (both sides use the same operation order; they differ only where
+libm differs); AMG hierarchy structure bit-exact; preconditioner
+applications to 1e-10; FGMRES iteration counts within +-2 of the oracle's
+(classical vs modified Gram-Schmidt); Newton fields to 1e-6 relative
+2-norm on pressure and saturation (the bar for the whole path), with
+linear solves converged to 1e-8.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1701_06254_amd import r2p
+    r2p.load()
+    return r2p
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _h(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _state_after(orc, w, steps):
+    """Oracle state after `steps` time steps (input for both sides)."""
+    m = orc.Model(w)
+    x = m.initial_state()
+    for _ in range(steps):
+        rc, *_ = m.newton_step(x, w["dt"])
+        assert rc == 0
+    return m, x
+
+
+def _blocks(rp, col, val):
+    d = {}
+    for i in range(len(rp) - 1):
+        for z in range(rp[i], rp[i + 1]):
+            d[(i, int(col[z]))] = np.asarray(val[z])
+    return d
+
+
+def _assert_blocks_close(dg, do, rtol, scale=None):
+    assert set(dg) == set(do)
+    if scale is None:
+        scale = max(np.abs(v).max() for v in do.values())
+    worst = max(np.abs(dg[k] - do[k]).max() for k in do)
+    assert worst <= rtol * scale, worst / scale
+
+
+# ------------------------------------------------------------------ model
+def test_initial_state_matches(dev, orc):
+    w = workloads.make_small()
+    mg = dev.Model(w)
+    mo = orc.Model(w)
+    xg = _h(mg.initial_state())
+    xo = mo.initial_state()
+    assert np.abs(xg - xo).max() <= 1e-12 * np.abs(xo).max()
+
+
+@pytest.mark.parametrize("which", ["random", "newton"])
+def test_assembly_matches(dev, orc, which):
+    w = workloads.make_tiny(7, 5, 3, seed=2) if which == "random" else workloads.make_small()
+    mo = orc.Model(w)
+    if which == "random":
+        rng = np.random.default_rng(9)
+        x = workloads.random_state(w, rng)
+        xo = workloads.random_state(w, rng)
+        dt = 3.0
+    else:
+        mo, xo = _state_after(orc, w, 2)
+        rng = np.random.default_rng(4)                      # an iterate inside a step
+        x = xo.copy()
+        x[0:2 * mo.n:2] += rng.standard_normal(mo.n)
+        x[1:2 * mo.n:2] = np.clip(x[1:2 * mo.n:2] + 0.01 * rng.standard_normal(mo.n), 0, 1)
+        dt = w["dt"]
+    Jo, Fo = mo.jacobian(x, xo, dt)
+    mg = dev.Model(w)
+    J = dev.Jacobian(mg)
+    b = _h(J.assemble(_t(x), _t(xo), dt))
+    assert np.abs(b + Fo).max() <= 1e-12 * np.abs(Fo).max()
+    rp, col, val = J.export()
+    assert np.array_equal(rp, Jo.rp) and np.array_equal(col, Jo.col)
+    assert np.abs(val - Jo.val).max() <= 1e-12 * np.abs(Jo.val).max()
+    # scaled norm of the Newton test
+    assert abs(mg.residual_norm(_t(b), dt) - mo.scaled_norm(Fo, dt)) <= 1e-12 * mo.scaled_norm(Fo, dt)
+
+
+def test_spmv_matches(dev, orc):
+    w = workloads.make_tiny(9, 7, 4, seed=5)
+    mo = orc.Model(w)
+    rng = np.random.default_rng(3)
+    x = workloads.random_state(w, rng)
+    Jo, Fo = mo.jacobian(x, x, 2.0)
+    mg = dev.Model(w)
+    J = dev.Jacobian(mg)
+    J.assemble(_t(x), _t(x), 2.0)
+    v = rng.standard_normal(mo.N)
+    yg = _h(J.spmv(_t(v)))
+    yo = Jo.matvec(v)
+    assert np.abs(yg - yo).max() <= 1e-13 * np.abs(yo).max()
+
+
+# ---------------------------------------------------------------- set-up
+def _setup_both(dev, orc, w, steps, copts_o, copts_g):
+    mo, x = _state_after(orc, w, steps)
+    Jo, Fo = mo.jacobian(x, x, w["dt"])
+    Ad, bd = orc.decouple(Jo, -Fo, mo.n, copts_o.decouple)
+    Po = orc.Cpr(Ad, mo, x, copts_o)
+    mg = dev.Model(w)
+    J = dev.Jacobian(mg)
+    b = J.assemble(_t(x), _t(x), w["dt"])
+    P = dev.Cpr().setup(J, copts_g)
+    return mo, x, Ad, bd, Po, mg, J, b, P
+
+
+@pytest.mark.parametrize("dec", [1, 2])
+def test_decoupled_matrix_matches(dev, orc, dec):
+    w = workloads.make_small()
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
+        dev, orc, w, 1, orc.cpr_opts(decouple=dec), dev.cpr_opts(decouple=dec))
+    rp, col, val = J.export()
+    assert np.array_equal(rp, Ad.rp) and np.array_equal(col, Ad.col)
+    assert np.abs(val - Ad.val).max() <= 1e-12 * np.abs(Ad.val).max()
+
+
+def test_amg_hierarchy_matches(dev, orc):
+    w = workloads.make_small()
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(dev, orc, w, 2, orc.cpr_opts(), dev.cpr_opts())
+    lo = Po.amg_levels()
+    lg = P.amg_levels()
+    assert len(lo) == len(lg) >= 2
+    for a, g in zip(lo, lg):
+        assert a["A"].n == g["n"]
+        assert np.array_equal(a["A"].rp, g["rp"]) and np.array_equal(a["A"].col, g["col"])
+        sc = np.abs(a["A"].val).max()
+        assert np.abs(a["A"].val - g["val"]).max() <= 1e-12 * sc
+        assert np.abs(a["l1"] - g["l1"]).max() <= 1e-12 * a["l1"].max()
+        if a["agg"] is not None:
+            assert np.array_equal(a["agg"], g["agg"])
+    # one V-cycle on a random right-hand side
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal(mo.n)
+    xg = _h(P.amg_vcycle(_t(f)))
+    xo = Po.amg_vcycle(f)
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_ras_factors_match(dev, orc, order):
+    w = workloads.make_small()
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
+        dev, orc, w, 2, orc.cpr_opts(order=order), dev.cpr_opts(order=order))
+    subs = Po.subdomains()
+    assert P.ras_info() == len(subs) == 16
+    for s, so in enumerate(subs):
+        sg = P.ras_subdomain(s)
+        glob_o = so["glob"]
+        assert set(sg["glob"]) == set(glob_o)
+        own_o = {int(g): bool(o) for g, o in zip(glob_o, so["owned"])}
+        assert all(own_o[int(g)] == bool(o) for g, o in zip(sg["glob"], sg["owned"]))
+        # factor blocks keyed by global (row, column)
+        LU = so["LU"]
+        do = {}
+        for a in range(LU.nb):
+            for z in range(LU.rp[a], LU.rp[a + 1]):
+                c = LU.col[z]
+                if c != a:
+                    do[(int(glob_o[a]), int(glob_o[c]))] = LU.val[z]
+        dg = {(int(r), int(c)): v for r, c, v in zip(sg["erow"], sg["ecol"], sg["eval"])}
+        _assert_blocks_close(dg, do, 1e-12)
+        dio = {int(g): d for g, d in zip(glob_o, so["dinv"])}
+        dig = {int(g): d for g, d in zip(sg["glob"], sg["dinv"])}
+        _assert_blocks_close(dig, dio, 1e-12)
+        # level order is a topological order of the oracle's local order
+        pos_o = {int(g): i for i, g in enumerate(glob_o)}
+        lev = {int(g): int(l) for g, l in zip(sg["glob"], sg["level"])}
+        for (r, c) in do:
+            if pos_o[c] < pos_o[r]:
+                assert lev[c] < lev[r]
+    rng = np.random.default_rng(1)
+    r = rng.standard_normal(mo.N)
+    yg = _h(P.ras_apply(_t(r)))
+    yo = Po.ras_apply(r)
+    assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(yo)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_cpr_apply_matches(dev, orc, form):
+    w = workloads.make_small()
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
+        dev, orc, w, 2, orc.cpr_opts(form=form), dev.cpr_opts(form=form))
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal(mo.N)
+    f[2 * mo.n + 1::2] = 0.0
+    zg = _h(P.apply(_t(f)))
+    zo = Po.apply(f)
+    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_fgmres_solve_matches(dev, orc, form):
+    w = workloads.make_small()
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
+        dev, orc, w, 3, orc.cpr_opts(form=form), dev.cpr_opts(form=form))
+    yo, st, its_o, rr_o = orc.fgmres(Ad, bd, Po)
+    assert st == 0
+    yg, info = dev.solve(J, P, b)
+    assert info.status == 0 and info.relres <= 1e-8
+    assert abs(info.iterations - its_o) <= 2
+    yg = _h(yg)
+    # both solutions satisfy the decoupled system to 1e-8; compare in the
+    # A-weighted sense: the difference is within what the residuals allow
+    A = Ad.to_scipy()
+    assert np.linalg.norm(bd - A @ yg) <= 1.000001e-8 * np.linalg.norm(bd)
+
+
+def test_newton_steps_match_oracle(dev, orc):
+    """Quarter five-spot (2,000 cells), 10 steps of 10 days: fields within
+    1e-6 relative 2-norm of the oracle on p and s_w."""
+    w = workloads.make_small()
+    mo = orc.Model(w)
+    xo = mo.initial_state()
+    mg = dev.Model(w)
+    xg = mg.initial_state()
+    n = mo.n
+    for step in range(w["steps"]):
+        rc, ni, li, _ = mo.newton_step(xo, w["dt"])
+        assert rc == 0
+        info = mg.newton_step(xg, w["dt"])
+        assert info.status == 0
+        assert abs(info.newton_its - ni) <= 2
+    xh = _h(xg)
+    for sl in (slice(0, 2 * n, 2), slice(1, 2 * n, 2)):
+        assert np.linalg.norm(xh[sl] - xo[sl]) <= 1e-6 * np.linalg.norm(xo[sl])

@@ -232,12 +232,34 @@ def test_amg_hierarchy_structure(oracle_lib):
             off = -row.copy()
             off[i] = -np.inf
             assert -row[j] > 0 and -row[j] >= 0.25 * off.max()
+    # one pass: each aggregate is one pair or singleton plus rows that joined
+    # it through a strong coupling to one of its paired members
+    agg1, nc1 = oracle_lib.aggregate(App)
+    assert agg1.max() + 1 == nc1 and len(np.unique(agg1)) == nc1
+    for I in range(nc1):
+        mem = np.nonzero(agg1 == I)[0]
+        paired = [i for i in mem if match[i] >= 0]
+        assert len(paired) in (0, 2)
+        if not paired:
+            assert len(mem) == 1
+        else:
+            for i in mem:
+                if match[i] < 0:
+                    row = A.getrow(i).toarray().ravel()
+                    assert min(row[paired]) < 0
+    # aggregates are numbered by their leader (smaller row of the pair, or the singleton)
+    leaders = []
+    for I in range(nc1):
+        mem = np.nonzero(agg1 == I)[0]
+        paired = [i for i in mem if match[i] >= 0]
+        leaders.append(min(paired) if paired else mem[0])
+    assert np.all(np.diff(leaders) > 0)
     H = oracle_lib.Amg(App, max_coarse=50)
     assert H.nlev >= 3
     for l in range(H.nlev - 1):
         lv, nxt = H.level(l), H.level(l + 1)
         agg = lv["agg"]
-        assert np.bincount(agg).max() <= 4
+        assert nxt["A"].n < lv["A"].n
         Pm = np.zeros((lv["A"].n, nxt["A"].n))
         Pm[np.arange(lv["A"].n), agg] = 1.0
         Af = lv["A"].to_scipy().toarray()
