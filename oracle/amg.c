@@ -108,25 +108,76 @@ void om_join_targets(const om_csr *A, double theta, const int *match, int *jt)
     }
 }
 
-/* Aggregates of one pass: pairs plus the rows that join them, and the
- * remaining singletons, numbered by their leader (the smaller row
- * of the pair, or the singleton). */
-int om_aggregate(const om_csr *A, double theta, int rounds, int *agg)
+/* Aggregates of one pass: pairs, the rows that join them, and the remaining
+ * singletons, numbered by their leader (the smaller row of the pair, or the
+ * singleton).  Joining is bounded: in each of `join_rounds` rounds every row
+ * still alone proposes to the pair of its strongest strong neighbour that
+ * belongs to a pair, and each pair takes only its strongest proposer (the
+ * proposer's coupling rounded to single precision, ties to the smaller
+ * row), so an aggregate holds at most 2 + join_rounds rows.  With
+ * join_rounds < 0 every proposer joins (unbounded). */
+int om_aggregate_bounded(const om_csr *A, double theta, int rounds, int join_rounds, int *agg)
 {
     int n = A->n;
     int *match = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
     int *jt = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    int *lead = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));   /* pair leader or -1 */
+    unsigned long long *best = (unsigned long long *)malloc(sizeof(unsigned long long) * (n > 0 ? n : 1));
     om_strength_match(A, theta, rounds, match);
-    om_join_targets(A, theta, match, jt);
+    for (int i = 0; i < n; i++) lead[i] = match[i] >= 0 ? (i < match[i] ? i : match[i]) : -1;
+    if (join_rounds < 0) {
+        om_join_targets(A, theta, match, jt);
+        for (int i = 0; i < n; i++)
+            if (match[i] < 0 && jt[i] >= 0) lead[i] = -2 - lead[jt[i]];   /* joined, mark */
+        for (int i = 0; i < n; i++)
+            if (lead[i] <= -2) lead[i] = -2 - lead[i];
+    }
+    for (int r = 0; r < join_rounds; r++) {
+        /* proposals: strongest strong neighbour that is in a pair aggregate */
+        for (int i = 0; i < n; i++) best[i] = 0ull;
+        for (int i = 0; i < n; i++) {
+            jt[i] = -1;
+            if (lead[i] >= 0) continue;
+            double mx = 0.0;
+            for (int z = A->rp[i]; z < A->rp[i + 1]; z++)
+                if (A->col[z] != i && -A->val[z] > mx) mx = -A->val[z];
+            double thr = theta * mx, bs = 0.0;
+            for (int z = A->rp[i]; z < A->rp[i + 1]; z++) {
+                int j = A->col[z];
+                double s = -A->val[z];
+                if (j == i || lead[j] < 0 || !(s > 0.0) || s < thr) continue;
+                if (s > bs) { bs = s; jt[i] = j; }
+            }
+            if (jt[i] >= 0) {
+                float f = (float)bs;
+                unsigned int fb;
+                memcpy(&fb, &f, sizeof(fb));
+                unsigned long long key = ((unsigned long long)fb << 32) | (0xFFFFFFFFull - (unsigned)i);
+                int L = lead[jt[i]];
+                if (key > best[L]) best[L] = key;
+            }
+        }
+        /* acceptance: the pair keeps its strongest proposer */
+        for (int i = 0; i < n; i++) {
+            if (jt[i] < 0) continue;
+            int L = lead[jt[i]];
+            if ((unsigned)(0xFFFFFFFFull - (best[L] & 0xFFFFFFFFull)) == (unsigned)i) lead[i] = -2 - L;
+        }
+        for (int i = 0; i < n; i++)
+            if (lead[i] <= -2) lead[i] = -2 - lead[i];
+    }
     int nc = 0;
     for (int i = 0; i < n; i++)
-        if ((match[i] >= 0 && i < match[i]) || (match[i] < 0 && jt[i] < 0)) agg[i] = nc++;
+        if ((match[i] >= 0 && i < match[i]) || lead[i] < 0) agg[i] = nc++;
     for (int i = 0; i < n; i++)
-        if (match[i] >= 0 && match[i] < i) agg[i] = agg[match[i]];
-    for (int i = 0; i < n; i++)
-        if (match[i] < 0 && jt[i] >= 0) agg[i] = agg[jt[i]];
-    free(match); free(jt);
+        if (lead[i] >= 0 && lead[i] != i) agg[i] = agg[lead[i]];
+    free(match); free(jt); free(lead); free(best);
     return nc;
+}
+
+int om_aggregate(const om_csr *A, double theta, int rounds, int *agg)
+{
+    return om_aggregate_bounded(A, theta, rounds, -1, agg);
 }
 
 static int cmp_int(const void *a, const void *b)

@@ -166,6 +166,7 @@ void om_strength_match(const om_csr *A, double theta, int rounds, int *match);
 void om_galerkin(const om_csr *A, const int *agg, int nc, om_csr *Ac);
 void om_join_targets(const om_csr *A, double theta, const int *match, int *jt);
 int  om_aggregate(const om_csr *A, double theta, int rounds, int *agg);
+int  om_aggregate_bounded(const om_csr *A, double theta, int rounds, int join_rounds, int *agg);
 
 /* solver.c */
 int  om_cpr_setup(om_cpr *P, const om_bsr *Adec, const om_model *mdl, const double *x,

@@ -58,6 +58,26 @@ __global__ void k_app_vals(int n, const int *rp, const int *slot, const double2 
     for (int z = rp[c]; z < rp[c + 1]; z++) val[z] = vp[(long)slot[z] * n + c].x;
 }
 
+// The same level-0 operator in the 7-slot stencil layout of the Jacobian
+// (absent neighbours hold 0), for the coalesced level-0 cycle kernels.
+__global__ void k_app_v7(int n, const double2 *vp, double *v7) {
+    long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (t < 7L * n) v7[t] = vp[t].x;
+}
+
+// Next-level rows with more than BIG members are restricted by a wavefront.
+constexpr int BIG = 16;
+__global__ void k_big_flag(int nc, const int *mptr, int *flag) {
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < nc) flag[I] = mptr[I + 1] - mptr[I] > BIG;
+    if (I == nc) flag[I] = 0;
+}
+
+__global__ void k_big_list(int nc, const int *mptr, const int *scan, int *big) {
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < nc && mptr[I + 1] - mptr[I] > BIG) big[scan[I]] = I;
+}
+
 // ------------------------------------------------------------- matching
 __global__ void k_strength_thr(int n, const int *rp, const int *col, const double *val,
                                double theta, double *thr, int *match) {
@@ -419,6 +439,14 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
     R2P_TRY(L0.val.ensure(L0.nnz));
     k_app_vals<<<r2p_blocks(n, BS), BS, 0, s>>>(n, L0.rp.p, P->iscratch2.p, J->vp.p, L0.val.p);
     R2P_LAUNCH();
+    R2P_TRY(L0.v7.ensure(7L * n));
+    k_app_v7<<<r2p_blocks(7L * n, BS), BS, 0, s>>>(n, J->vp.p, L0.v7.p);
+    R2P_LAUNCH();
+    if (P->o.precision == R2P_FP32) {
+        R2P_TRY(L0.v7f.ensure(7L * n));
+        k_castv<float><<<r2p_blocks(7L * n, BS), BS, 0, s>>>(7L * n, L0.v7.p, L0.v7f.p);
+        R2P_LAUNCH();
+    }
     int maxlev = std::min(std::max(P->o.max_levels, 1), 24);
     int passes = std::max(P->o.agg_passes, 1);
     int l = 0;
@@ -453,6 +481,19 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
         C.n = nc;
         C.nnz = nnzc;
         R2P_TRY(build_members(P, A.n, A.agg.p, nc, A.mptr, A.mem, s));
+        {
+            DBuf<int> flag;
+            R2P_TRY(flag.ensure(nc + 1));
+            k_big_flag<<<r2p_blocks(nc + 1, BS), BS, 0, s>>>(nc, A.mptr.p, flag.p);
+            R2P_LAUNCH();
+            int nbig = 0;
+            R2P_TRY(r2p_scan_int(flag.p, flag.p, nc + 1, &nbig, P->iscratch, P->pin, s));
+            R2P_TRY(A.big.ensure(nbig));
+            k_big_list<<<r2p_blocks(nc, BS), BS, 0, s>>>(nc, A.mptr.p, flag.p, A.big.p);
+            R2P_LAUNCH();
+            R2P_HIP(hipStreamSynchronize(s));
+            A.nbig = nbig;
+        }
         l++;
     }
     P->nlev = l + 1;
@@ -528,14 +569,77 @@ __global__ void k_down(DownArgs<T> A) {
     A.r[i] = r;
 }
 
-// Restriction P^T r: each coarse row sums its fine members in ascending order.
+// Restriction P^T r.  The first nbs workgroups give one thread per coarse
+// row (members summed in ascending order); the trailing workgroups give one
+// wavefront per row with more than BIG members (lanes stride over the
+// members, then a fixed butterfly reduction), so a few very large aggregates
+// do not serialise the launch.  Deterministic either way.
 template <class T>
-__global__ void k_restrict(int nc, const int *mptr, const int *mem, const T *r, T *bc) {
-    int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= nc) return;
-    T acc = (T)0;
-    for (int t = mptr[I]; t < mptr[I + 1]; t++) acc += r[mem[t]];
-    bc[I] = acc;
+__global__ void k_restrict(int nc, int nbs, const int *mptr, const int *mem, const int *big,
+                           int nbig, const T *r, T *bc) {
+    if ((int)blockIdx.x < nbs) {
+        int I = blockIdx.x * blockDim.x + threadIdx.x;
+        if (I >= nc) return;
+        int a = mptr[I], b = mptr[I + 1];
+        if (b - a > BIG) return;
+        T acc = (T)0;
+        for (int t = a; t < b; t++) acc += r[mem[t]];
+        bc[I] = acc;
+    } else {
+        int w = ((int)blockIdx.x - nbs) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        if (w >= nbig) return;
+        int lane = threadIdx.x & 63;
+        int I = big[w];
+        T acc = (T)0;
+        for (int t = mptr[I] + lane; t < mptr[I + 1]; t += 64) acc += r[mem[t]];
+        for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+        if (lane == 0) bc[I] = acc;
+    }
+}
+
+// Level 0 in the 7-slot layout: columns are implied by the grid (clamped at
+// the boundary, where the coefficient is 0) and summed in ascending order.
+template <class T>
+struct Level0 {
+    int n, nx, nxy;
+    const T *v7, *l1;
+    const double *f;
+    int fstride;
+};
+
+template <class T>
+__global__ void k_down0(Level0<T> A, T *x, T *r) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int order[7] = {5, 3, 1, 0, 2, 4, 6};
+    T bi = (T)A.f[(long)A.fstride * i];
+    x[i] = bi / A.l1[i];
+    T s = bi;
+#pragma unroll
+    for (int oi = 0; oi < 7; oi++) {
+        int sl = order[oi];
+        int j = i + slot_offset(sl, A.nx, A.nxy);
+        j = j < 0 ? 0 : (j >= A.n ? A.n - 1 : j);
+        s -= A.v7[(long)sl * A.n + i] * ((T)A.f[(long)A.fstride * j] / A.l1[j]);
+    }
+    r[i] = s;
+}
+
+template <class T>
+__global__ void k_up0(Level0<T> A, const int *agg, const T *x, const T *xc, double *xo) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int order[7] = {5, 3, 1, 0, 2, 4, 6};
+    T s = (T)A.f[(long)A.fstride * i];
+#pragma unroll
+    for (int oi = 0; oi < 7; oi++) {
+        int sl = order[oi];
+        int j = i + slot_offset(sl, A.nx, A.nxy);
+        j = j < 0 ? 0 : (j >= A.n ? A.n - 1 : j);
+        s -= A.v7[(long)sl * A.n + i] * (x[j] + xc[agg[j]]);
+    }
+    T xi = x[i] + xc[agg[i]];
+    xo[i] = (double)(xi + s / A.l1[i]);
 }
 
 template <class T>
@@ -609,20 +713,33 @@ static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStrea
         R2P_LAUNCH();
         return 0;
     }
+    const Phys &ph = P->J->m->ph;
+    Level0<T> Z;
+    Z.n = P->lv[0].n; Z.nx = ph.nx; Z.nxy = ph.nx * ph.ny;
+    if constexpr (sizeof(T) == 4) Z.v7 = P->lv[0].v7f.p; else Z.v7 = (const T *)P->lv[0].v7.p;
+    Z.l1 = l1s(P->lv[0]);
+    Z.f = f;
+    Z.fstride = fstride;
     for (int l = 0; l < nl - 1; l++) {
         AmgLevel &A = P->lv[l];
         AmgLevel &C = P->lv[l + 1];
         // the level's output buffer holds its residual until the up sweep
-        DownArgs<T> D;
-        D.n = A.n; D.rp = A.rp.p; D.col = A.col.p;
-        D.val = vals(A); D.l1 = l1s(A);
-        D.b = l == 0 ? nullptr : vb(A);
-        D.f = l == 0 ? f : nullptr;
-        D.fstride = fstride;
-        D.x = vx(A); D.r = vxo(A);
-        k_down<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(D);
+        if (l == 0) {
+            k_down0<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(Z, vx(A), vxo(A));
+        } else {
+            DownArgs<T> D;
+            D.n = A.n; D.rp = A.rp.p; D.col = A.col.p;
+            D.val = vals(A); D.l1 = l1s(A);
+            D.b = vb(A);
+            D.f = nullptr;
+            D.fstride = 1;
+            D.x = vx(A); D.r = vxo(A);
+            k_down<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(D);
+        }
         R2P_LAUNCH();
-        k_restrict<T><<<r2p_blocks(C.n, BS), BS, 0, s>>>(C.n, A.mptr.p, A.mem.p, vxo(A), vb(C));
+        int nbs = r2p_blocks(C.n, BS);
+        k_restrict<T><<<nbs + r2p_blocks(A.nbig, BS / 64), BS, 0, s>>>(
+            C.n, nbs, A.mptr.p, A.mem.p, A.big.p, A.nbig, vxo(A), vb(C));
         R2P_LAUNCH();
     }
     AmgLevel &Cst = P->lv[nl - 1];
@@ -632,6 +749,11 @@ static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStrea
     for (int l = nl - 2; l >= 0; l--) {
         AmgLevel &A = P->lv[l];
         AmgLevel &C = P->lv[l + 1];
+        if (l == 0) {
+            k_up0<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(Z, A.agg.p, vx(A), vxo(C), xp);
+            R2P_LAUNCH();
+            continue;
+        }
         UpArgs<T> U;
         U.n = A.n; U.rp = A.rp.p; U.col = A.col.p; U.agg = A.agg.p; U.val = vals(A); U.l1 = l1s(A);
         U.b = l == 0 ? nullptr : vb(A);

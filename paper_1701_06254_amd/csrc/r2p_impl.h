@@ -120,18 +120,20 @@ __host__ __device__ inline int slot_offset(int s, int nx, int nxy) {
 }
 
 // ------------------------------------------------------------------ RAS
-// Block ILU(0) factors of every overlapped subdomain, rows stored in level
-// order (rows of one level are independent).  Per local row p (global
-// position index into the concatenation of all subdomains):
-//   glob[p]    global block row;  owned[p] restricted-scatter flag
-//   eptr[p]..eptr[p+1]  off-diagonal factor blocks, the first nl[p] are L
-//                       (predecessors, ascending local order), then U
-//   ecol[e]    local position of the block's column row
-//   dinv[p]    inverse of U's diagonal block
+// Block ILU(0) factors of every overlapped subdomain.  Rows ("positions" p,
+// concatenated over subdomains) are stored in level order of each
+// subdomain's dependency graph, rows of a level sorted by descending number
+// of predecessors.  Every level is cut into slices of 64 consecutive
+// positions (one wavefront, one row per lane); a slice stores its L blocks
+// (predecessors, ascending local order) and its U blocks (successors) in
+// sliced-ELL form: entry e of lane t of slice k sits at base[k] + 64 e + t,
+// so each load instruction of a wavefront is contiguous.  Padding entries
+// (e >= the row's count) are never read.
+constexpr int RAS_SLICE = 64;
 template <class T>
 struct RasFactors {
-    DBuf<T> eval;     // 4 per block
-    DBuf<T> dinv;     // 4 per row
+    DBuf<T> lval, uval;   // 4 per entry (row-major 2x2)
+    DBuf<T> dinv;         // 4 per position: inverse of U's diagonal block
 };
 
 struct RasStatic {
@@ -149,20 +151,24 @@ struct RasStatic {
 
 struct RasDyn {
     int maxlev = 0;
-    std::vector<int> h_lptr;              // per subdomain level offsets (flattened)
+    int nseg = 0, nslice = 0, nlent = 0, nuent = 0;
     std::vector<int> h_nlev;              // levels per subdomain
-    std::vector<int> h_lbase;             // index into h_lptr per subdomain
+    std::vector<int> h_lbase;             // first segment (level) index per subdomain
     DBuf<int> lev;                        // mtot: level of local row (natural)
-    DBuf<int> pos;                        // mtot: position of local row in level order
+    DBuf<int> nlnat, nunat;               // mtot: predecessor / successor counts (natural)
+    DBuf<int> pos;                        // mtot: position of local row
     DBuf<int> perm;                       // mtot: local row (natural) at position
     DBuf<int> glob;                       // mtot: global row at position
     DBuf<unsigned char> owned;            // mtot
-    DBuf<int> eptr;                       // mtot+1
-    DBuf<int> nl;                         // mtot
-    DBuf<int> ecol;                       // nadj
-    DBuf<int> esrc;                       // nadj: block source per factor entry (setup only)
-    DBuf<int> lptr_dev;                   // flattened level pointers (positions)
-    DBuf<int> sub_lbase;                  // ns: base into lptr_dev
+    DBuf<int> nl, nu;                     // mtot: counts per position
+    DBuf<int> lptr_dev;                   // nseg+1: first position of every level
+    DBuf<int> soff;                       // nseg+1: first slice of every level
+    DBuf<int> sl_start, sl_cnt, sl_wl, sl_wu, sl_bl, sl_bu;   // per slice
+    DBuf<int> sl_of;                      // mtot: slice of every position
+    DBuf<int> lcol, ucol;                 // entries: column position (-1 padding)
+    DBuf<int> lsrc, usrc;                 // entries: block source (set-up only)
+    DBuf<int> dsrc_pos;                   // mtot: diagonal block source per position
+    DBuf<int> sub_lbase;                  // ns: first segment of the subdomain
     DBuf<int> sub_nlev;                   // ns
     DBuf<int> counters;                   // scratch
     RasFactors<double> f64;
@@ -182,6 +188,10 @@ struct AmgLevel {
     DBuf<double> val, l1;
     DBuf<int> agg;           // n: row of the next level
     DBuf<int> mptr, mem;     // next level's member lists (n_next+1, n)
+    DBuf<int> big;           // next-level rows with many members (restricted by a wavefront)
+    int nbig = 0;
+    DBuf<double> v7;         // level 0 only: A_pp in the 7-slot stencil layout (slot-major)
+    DBuf<float> v7f;
     AmgLevelT<float> f32;
     DBuf<double> b, x, xo;   // work vectors (fp64)
     DBuf<float> bf, xf, xof; // work vectors (fp32)
@@ -204,8 +214,8 @@ struct r2p_cpr {
     // level-0 structure cache
     int app_n = -1;
     // work vectors
-    DBuf<double> t_r, t_y, t_xp, t_ras;
-    DBuf<float> t_rasf;
+    DBuf<double> t_r, t_y, t_xp, t_ras, t_rl;
+    DBuf<float> t_rasf, t_rlf;
     DBuf<int> iscratch;
     DBuf<int> iscratch2;
     DBuf<double> dscratch;
@@ -229,7 +239,36 @@ int r2p_scan_int(const int *in, int *out, int n, int *total_host, DBuf<int> &tmp
 
 inline int r2p_blocks(long n, int bs) { return (int)((n + bs - 1) / bs); }
 
+// Source of a Jacobian block for the subdomain matrices: >= 0 is a slot block
+// index (slot*n + row) into vp/vs; -(1+q) the cell row's well column cw[q];
+// -(1+nperf+q) the well row's cell block wc[q]; -(1+2*nperf+w) the well
+// diagonal [[wd[w], 0], [0, 1]].
+struct BlkSrc {
+    const double2 *vp, *vs, *cw, *wc;
+    const double *wd;
+    int nperf;
+};
+
+__device__ __forceinline__ void load_block(const BlkSrc &B, int src, double *a) {
+    if (src >= 0) {
+        double2 p = B.vp[src], s = B.vs[src];
+        a[0] = p.x; a[1] = s.x; a[2] = p.y; a[3] = s.y;
+    } else {
+        int t = -src - 1;
+        if (t < B.nperf) {
+            double2 c = B.cw[t];
+            a[0] = c.x; a[1] = 0.0; a[2] = c.y; a[3] = 0.0;
+        } else if (t < 2 * B.nperf) {
+            double2 c = B.wc[t - B.nperf];
+            a[0] = c.x; a[1] = c.y; a[2] = 0.0; a[3] = 0.0;
+        } else {
+            a[0] = B.wd[t - 2 * B.nperf]; a[1] = 0.0; a[2] = 0.0; a[3] = 1.0;
+        }
+    }
+}
+
 // Internal entry points shared between translation units.
+int r2p_ras_static(r2p_cpr *P, hipStream_t s);
 int r2p_cpr_apply_impl(r2p_cpr *P, const double *f, double *z, hipStream_t s);
 int r2p_spmv_impl(r2p_jacobian *J, const double *x, double *y, const double *f, hipStream_t s);
 int r2p_decouple_rhs(r2p_jacobian *J, const double *b, double *bd, hipStream_t s);

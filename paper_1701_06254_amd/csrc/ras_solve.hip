@@ -1,0 +1,758 @@
+// Block ILU(0) set-up and application for the RAS stage, on the local order
+// of every subdomain ("Local potential reordering technique", Eq 30-33; RAS
+// stage R(A)^-1 of Algorithm 2).
+//
+// Device design.  ILU(0) and its triangular solves depend only on which end
+// of every coupling comes first in the local order, so the rows of each
+// subdomain are grouped into levels of the dependency graph (longest-path
+// depth); rows of a level are independent.  Inside a row, predecessors and
+// successors stay in local order, so every block update happens in the same
+// sequence as a sequential ILU(0) in that order and the factors match it.
+//
+// One workgroup (16 wavefronts) processes one subdomain level by level, a
+// workgroup barrier between levels; a wavefront takes a 64-row slice, one
+// row per lane.  Levels are a latency chain, so every wavefront fetches the
+// static data of its next slice (factor blocks, columns, right-hand side)
+// into registers right after issuing the current slice's dependent loads:
+// loads retire in issue order, so waiting for the current rows never waits
+// for the prefetch, and the prefetch overlaps the compute, the store and the
+// barrier.  The gather of the right-hand side into local order and the
+// restricted scatter of the result run as separate full-device kernels.
+//
+// Compiled without floating-point contraction (reproducible block products).
+#include <algorithm>
+#include <cstring>
+
+#include "r2p_impl.h"
+
+constexpr int BS = 256;
+constexpr int WG = 1024;               // threads of a subdomain workgroup
+constexpr int NWAVE = WG / 64;
+constexpr int MAXW = 4;                // blocks per row held in registers
+constexpr int MAXLEV = 4096;           // levels per subdomain kept in LDS
+
+// True when global row h precedes global row g in the local order.
+__device__ __forceinline__ bool before(int h, int g, int n, int order, const double *phi) {
+    bool hc = h < n, gc = g < n;
+    if (hc != gc) return hc;            // cells before wells
+    if (!hc || order == R2P_ORDER_NATURAL) return h < g;
+    double a = phi[h], b = phi[g];
+    return a > b || (a == b && h < g);
+}
+
+// ------------------------------------------------------------------ levels
+// Longest-path level, relaxed in place until nothing changes (levels only
+// grow and are bounded, so the fixed point is the longest-path depth).
+__global__ void k_levels(int mtot, int n, int order, const double *phi, const int *glob_nat,
+                         const int *aptr, const int *adj, int *lev, int *changed) {
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= mtot) return;
+    int g = glob_nat[l];
+    int best = 0;
+    for (int e = aptr[l]; e < aptr[l + 1]; e++) {
+        int h = adj[e];
+        if (before(glob_nat[h], g, n, order, phi)) {
+            int v = __hip_atomic_load(&lev[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+            best = v > best ? v : best;
+        }
+    }
+    int cur = lev[l];
+    if (best > cur) {
+        __hip_atomic_store(&lev[l], best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *changed = 1;
+    }
+}
+
+__global__ void k_pred_count(int mtot, int n, int order, const double *phi, const int *glob_nat,
+                             const int *aptr, const int *adj, int *nl, int *nu) {
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= mtot) return;
+    int g = glob_nat[l], a = 0;
+    for (int e = aptr[l]; e < aptr[l + 1]; e++) a += before(glob_nat[adj[e]], g, n, order, phi);
+    nl[l] = a;
+    nu[l] = aptr[l + 1] - aptr[l] - a;
+}
+
+// Deepest level of every subdomain: rows of a subdomain are contiguous, so a
+// workgroup meets at most a few subdomains; it reduces in LDS first.
+__global__ void k_sub_maxlev(int mtot, int ns, const int *sub_of, const int *lev, int *mx) {
+    __shared__ int smax[64];
+    if (threadIdx.x < 64) smax[threadIdx.x] = 0;
+    __syncthreads();
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < mtot) atomicMax(&smax[sub_of[l]], lev[l]);
+    __syncthreads();
+    if (threadIdx.x < ns && smax[threadIdx.x] > 0) atomicMax(&mx[threadIdx.x], smax[threadIdx.x]);
+}
+
+__global__ void k_level_count(int mtot, const int *sub_of, const int *lev, const int *lbase,
+                              int *cnt) {
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= mtot) return;
+    atomicAdd(&cnt[lbase[sub_of[l]] + lev[l]], 1);
+}
+
+// Sort key of a row: its level segment, then descending predecessor count
+// (so the widest rows of a level share slices); the sort is stable, rows with
+// equal keys stay in natural local order.
+__global__ void k_order_keys(int mtot, const int *sub_of, const int *lev, const int *lbase,
+                             const int *nl, unsigned *key, unsigned *val) {
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= mtot) return;
+    unsigned seg = (unsigned)(lbase[sub_of[l]] + lev[l]);
+    unsigned w = 7u - (unsigned)min(nl[l], 7);
+    key[l] = (seg << 3) | w;
+    val[l] = (unsigned)l;
+}
+
+__global__ void k_perm_gather(int mtot, const unsigned *perm, const int *glob_nat,
+                              const unsigned char *owned_nat, const int *nlnat, const int *nunat,
+                              const int *dsrc_nat, int *pos, int *permi, int *glob,
+                              unsigned char *owned, int *nl, int *nu, int *dsrc) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= mtot) return;
+    int l = (int)perm[p];
+    permi[p] = l;
+    pos[l] = p;
+    glob[p] = glob_nat[l];
+    owned[p] = owned_nat[l];
+    nl[p] = nlnat[l];
+    nu[p] = nunat[l];
+    dsrc[p] = dsrc_nat[l];
+}
+
+__global__ void k_slice_count(int nseg, const int *lptr, int *nsl) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < nseg) nsl[g] = (lptr[g + 1] - lptr[g] + RAS_SLICE - 1) / RAS_SLICE;
+    if (g == nseg) nsl[g] = 0;
+}
+
+// One thread per slice: rows, widths, and the slice of every position.
+__global__ void k_slice_fill(int nseg, const int *lptr, const int *soff, int nslice,
+                             const int *nl, const int *nu, int *st, int *cn, int *wl, int *wu,
+                             int *sl_of) {
+    int g = blockIdx.x;             // one workgroup per level segment
+    if (g >= nseg) return;
+    int a = soff[g], b = soff[g + 1];
+    for (int sl = a + (int)threadIdx.x; sl < b; sl += blockDim.x) {
+        int start = lptr[g] + (sl - a) * RAS_SLICE;
+        int cnt = min(RAS_SLICE, lptr[g + 1] - start);
+        int ml = 0, mu = 0;
+        for (int t = 0; t < cnt; t++) {
+            ml = max(ml, nl[start + t]);
+            mu = max(mu, nu[start + t]);
+            sl_of[start + t] = sl;
+        }
+        st[sl] = start;
+        cn[sl] = cnt;
+        wl[sl] = ml;
+        wu[sl] = mu;
+    }
+}
+
+__global__ void k_slice_size(int nslice, const int *w, int *sz) {
+    int sl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl < nslice) sz[sl] = w[sl] * RAS_SLICE;
+    if (sl == nslice) sz[sl] = 0;
+}
+
+// Entries of position p in its slice: predecessors and successors, each in
+// ascending local order (insertion sort over the strided slots).
+__global__ void k_fill_entries(int mtot, int n, int order, const double *phi, const int *permi,
+                               const int *glob_nat, const int *aptr, const int *adj,
+                               const int *asrc, const int *pos, const int *glob, const int *sl_of,
+                               const int *sl_st, const int *sl_bl, const int *sl_bu, int *lcol,
+                               int *lsrc, int *ucol, int *usrc) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= mtot) return;
+    int l = permi[p], g = glob_nat[l];
+    int sl = sl_of[p], lane = p - sl_st[sl];
+    long bl = (long)sl_bl[sl] + lane, bu = (long)sl_bu[sl] + lane;
+    int el = 0, eu = 0;
+    for (int t = aptr[l]; t < aptr[l + 1]; t++) {
+        int h = adj[t];
+        int gh = glob_nat[h];
+        if (before(gh, g, n, order, phi)) {
+            long k = bl + (long)el * RAS_SLICE;
+            lcol[k] = pos[h];
+            lsrc[k] = asrc[t];
+            el++;
+        } else {
+            long k = bu + (long)eu * RAS_SLICE;
+            ucol[k] = pos[h];
+            usrc[k] = asrc[t];
+            eu++;
+        }
+    }
+    for (int part = 0; part < 2; part++) {
+        int cnt = part == 0 ? el : eu;
+        long b = part == 0 ? bl : bu;
+        int *col = part == 0 ? lcol : ucol;
+        int *src = part == 0 ? lsrc : usrc;
+        for (int u = 1; u < cnt; u++) {
+            int vc = col[b + (long)u * RAS_SLICE], vs = src[b + (long)u * RAS_SLICE];
+            int vg = glob[vc];
+            int k = u - 1;
+            while (k >= 0 && before(vg, glob[col[b + (long)k * RAS_SLICE]], n, order, phi)) {
+                col[b + (long)(k + 1) * RAS_SLICE] = col[b + (long)k * RAS_SLICE];
+                src[b + (long)(k + 1) * RAS_SLICE] = src[b + (long)k * RAS_SLICE];
+                k--;
+            }
+            col[b + (long)(k + 1) * RAS_SLICE] = vc;
+            src[b + (long)(k + 1) * RAS_SLICE] = vs;
+        }
+    }
+}
+
+// ---------------------------------------------------------- factorisation
+struct FactArgs {
+    BlkSrc B;
+    const int *lbase, *nlev, *soff;
+    const int *sl_st, *sl_cn, *sl_bl, *sl_bu, *sl_of;
+    const int *nl, *nu, *dsrc, *lcol, *ucol, *lsrc, *usrc;
+    double *lval, *uval, *dinv;
+    int *status;
+};
+
+// Block ILU(0), one workgroup per subdomain, level by level (IKJ form):
+// for every predecessor q in local order: L_pq = A_pq U_qq^-1, then
+// A_pj -= L_pq U_qj for each later entry j of row p that row q also holds.
+__global__ __launch_bounds__(WG) void k_bilu0(FactArgs A) {
+    int s = blockIdx.x;
+    int nlev = A.nlev[s], base = A.lbase[s];
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int L = 0; L < nlev; L++) {
+        int s0 = A.soff[base + L], s1 = A.soff[base + L + 1];
+        for (int sl = s0 + wave; sl < s1; sl += NWAVE) {
+            if (lane >= A.sl_cn[sl]) continue;
+            int p = A.sl_st[sl] + lane;
+            long bl = (long)A.sl_bl[sl] + lane, bu = (long)A.sl_bu[sl] + lane;
+            int nlp = A.nl[p], nup = A.nu[p];
+            for (int e = 0; e < nlp; e++) {
+                long k = bl + (long)e * RAS_SLICE;
+                load_block(A.B, A.lsrc[k], &A.lval[4 * k]);
+            }
+            for (int e = 0; e < nup; e++) {
+                long k = bu + (long)e * RAS_SLICE;
+                load_block(A.B, A.usrc[k], &A.uval[4 * k]);
+            }
+            double d[4];
+            load_block(A.B, A.dsrc[p], d);
+            for (int e = 0; e < nlp; e++) {
+                long k = bl + (long)e * RAS_SLICE;
+                int q = A.lcol[k];
+                double *a = &A.lval[4 * k];
+                const double *dk = &A.dinv[4 * (long)q];
+                double l0 = a[0] * dk[0] + a[1] * dk[2];
+                double l1 = a[0] * dk[1] + a[1] * dk[3];
+                double l2 = a[2] * dk[0] + a[3] * dk[2];
+                double l3 = a[2] * dk[1] + a[3] * dk[3];
+                a[0] = l0; a[1] = l1; a[2] = l2; a[3] = l3;
+                int sq = A.sl_of[q];
+                long buq = (long)A.sl_bu[sq] + (q - A.sl_st[sq]);
+                int nuq = A.nu[q];
+                // later entries of row p: remaining predecessors, the diagonal, successors
+                for (int e2 = e + 1; e2 <= nlp + nup; e2++) {
+                    int cj;
+                    double *t;
+                    if (e2 < nlp) { long k2 = bl + (long)e2 * RAS_SLICE; cj = A.lcol[k2]; t = &A.lval[4 * k2]; }
+                    else if (e2 == nlp) { cj = p; t = d; }
+                    else { long k2 = bu + (long)(e2 - nlp - 1) * RAS_SLICE; cj = A.ucol[k2]; t = &A.uval[4 * k2]; }
+                    for (int y = 0; y < nuq; y++) {
+                        long ky = buq + (long)y * RAS_SLICE;
+                        if (A.ucol[ky] == cj) {
+                            const double *u = &A.uval[4 * ky];
+                            t[0] -= l0 * u[0] + l1 * u[2];
+                            t[1] -= l0 * u[1] + l1 * u[3];
+                            t[2] -= l2 * u[0] + l3 * u[2];
+                            t[3] -= l2 * u[1] + l3 * u[3];
+                            break;
+                        }
+                    }
+                }
+            }
+            double det = d[0] * d[3] - d[1] * d[2];
+            if (det == 0.0 || det != det) atomicOr(A.status, 1);
+            double *di = &A.dinv[4 * (long)p];
+            di[0] = d[3] / det; di[1] = -d[1] / det; di[2] = -d[2] / det; di[3] = d[0] / det;
+        }
+        __syncthreads();
+    }
+}
+
+template <class T>
+__global__ void k_cast(long n, const double *a, T *b) {
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (T)a[i];
+}
+
+// ------------------------------------------------------------------ solve
+template <class T>
+__global__ void k_ras_gather(int mtot, const int *glob, const double *r, T *rl) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= mtot) return;
+    long g = glob[p];
+    rl[2 * (long)p] = (T)r[2 * g];
+    rl[2 * (long)p + 1] = (T)r[2 * g + 1];
+}
+
+// Restricted scatter: owned rows only; optional Pi_p addend on the pressure
+// and accumulation into out (out = (out + Pi_p xp) + z, Algorithm 2's order).
+template <class T>
+__global__ void k_ras_scatter(int mtot, int n, const int *glob, const unsigned char *owned,
+                              const T *y, const double *xp, int accumulate, double *out) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= mtot || !owned[p]) return;
+    long g = glob[p];
+    double o0 = (double)y[2 * (long)p], o1 = (double)y[2 * (long)p + 1];
+    if (accumulate) {
+        double v0 = out[2 * g];
+        if (xp && g < n) v0 += xp[g];
+        out[2 * g] = v0 + o0;
+        out[2 * g + 1] += o1;
+    } else {
+        if (xp && g < n) o0 += xp[g];
+        out[2 * g] = o0;
+        out[2 * g + 1] = o1;
+    }
+}
+
+template <class T>
+struct SweepArgs {
+    const int *lbase, *nlev, *soff;
+    const int *sl_st, *sl_cn, *sl_bl, *sl_bu, *sl_wl, *sl_wu;
+    const int *nl, *nu, *lcol, *ucol;
+    const T *lval, *uval, *dinv, *rl;
+    T *y;
+    int mtot;  // local rows over all subdomains: the extent of y
+};
+
+// A row's static data held in registers: for the forward sweep the gathered
+// right-hand side and the first MAXW L blocks, for the backward sweep the
+// forward result, the first MAXW U blocks and the inverse diagonal.  Loads
+// are unconditional (slots past a row's count or a slice's width read the
+// zero padding or this row itself) so the fetch has no data-dependent branch.
+template <class T>
+struct Row {
+    int p, n, base;
+    bool valid;
+    T a0, a1;
+    int col[MAXW];
+    T v[MAXW][4];
+    T d[4];
+};
+
+template <class T, bool FWD>
+__device__ __forceinline__ void fetch_row(Row<T> &R, const SweepArgs<T> &A, int sl, int lane) {
+    int sls = sl < 0 ? 0 : sl;                       // wave-uniform
+    int cnt = A.sl_cn[sls], st = A.sl_st[sls];
+    int w = FWD ? A.sl_wl[sls] : A.sl_wu[sls];
+    int b = FWD ? A.sl_bl[sls] : A.sl_bu[sls];
+    R.valid = sl >= 0 && lane < cnt;
+    int p = st + (lane < cnt ? lane : 0);
+    R.p = p;
+    R.base = b + lane;
+    // lanes past the slice's rows see only padding columns (-1): they take
+    // no blocks, so every column a lane dereferences is a real local row
+    int nrow = FWD ? A.nl[p] : A.nu[p];
+    R.n = R.valid ? nrow : 0;
+    if (FWD) { R.a0 = A.rl[2 * (long)p]; R.a1 = A.rl[2 * (long)p + 1]; }
+    else { R.a0 = A.y[2 * (long)p]; R.a1 = A.y[2 * (long)p + 1]; }
+    const int *cols = FWD ? A.lcol : A.ucol;
+    const T *vals = FWD ? A.lval : A.uval;
+#pragma unroll
+    for (int e = 0; e < MAXW; e++) {
+        // Loads are unconditional so that the wait counts stay exact; columns
+        // past the slice width re-read its last column (or, for an empty
+        // slice, the padding that follows the entry arrays) and are masked
+        // by the row length later.
+        int ee = e < w ? e : (w > 0 ? w - 1 : 0);
+        long k = (long)R.base + (long)ee * RAS_SLICE;
+        R.col[e] = cols[k];
+        R.v[e][0] = vals[4 * k]; R.v[e][1] = vals[4 * k + 1];
+        R.v[e][2] = vals[4 * k + 2]; R.v[e][3] = vals[4 * k + 3];
+    }
+    if (!FWD) {
+        const T *di = &A.dinv[4 * (long)p];
+        R.d[0] = di[0]; R.d[1] = di[1]; R.d[2] = di[2]; R.d[3] = di[3];
+    }
+}
+
+// Next slice this wavefront works on after slice `sl` of level `L` (sweeping
+// up when dir > 0, down otherwise), or level -1 / nlev when there is none.
+__device__ __forceinline__ void next_task(const int *soff, int nlev, int dir, int wave, int &L,
+                                          int &sl) {
+    if (sl >= 0 && sl + NWAVE < soff[L + 1]) { sl += NWAVE; return; }
+    for (L += dir; L >= 0 && L < nlev; L += dir)
+        if (soff[L] + wave < soff[L + 1]) { sl = soff[L] + wave; return; }
+    sl = -1;
+}
+
+// One row of a sweep: t = a - sum_e B_e y_{col_e} over the row's blocks in
+// order, the first MAXW from registers, any further ones loaded here.
+template <class T>
+__device__ __forceinline__ void row_update(const Row<T> &R, const T *y0, const T *y1,
+                                           const int *cols, const T *vals, const T *y, int mtot,
+                                           T &t0, T &t1) {
+    t0 = R.a0;
+    t1 = R.a1;
+#pragma unroll
+    for (int e = 0; e < MAXW; e++) {
+        T d0 = R.v[e][0] * y0[e] + R.v[e][1] * y1[e];
+        T d1 = R.v[e][2] * y0[e] + R.v[e][3] * y1[e];
+        bool on = e < R.n;
+        t0 -= on ? d0 : (T)0;
+        t1 -= on ? d1 : (T)0;
+    }
+    for (int e = MAXW; e < R.n; e++) {
+        long k = (long)R.base + (long)e * RAS_SLICE;
+        long q = cols[k];
+        q = (unsigned long)q < (unsigned long)mtot ? q : (long)R.p;
+        T a0 = y[2 * q], a1 = y[2 * q + 1];
+        t0 -= vals[4 * k] * a0 + vals[4 * k + 1] * a1;
+        t1 -= vals[4 * k + 2] * a0 + vals[4 * k + 3] * a1;
+    }
+}
+
+// Forward (L) then backward (U) substitution of one subdomain per workgroup
+// on the gathered right-hand side; the result overwrites y in local order.
+// In each step a wavefront issues the loads its current rows depend on,
+// then fetches its next slice, then computes and stores.
+template <class T>
+__global__ __launch_bounds__(WG) void k_ras_sweep(SweepArgs<T> A) {
+    __shared__ int soff[MAXLEV + 1];
+    int s = blockIdx.x;
+    int nlev = A.nlev[s], base = A.lbase[s];
+    for (int L = threadIdx.x; L <= nlev; L += WG) soff[L] = A.soff[base + L];
+    __syncthreads();
+    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    for (int dir = 1; dir >= -1; dir -= 2) {
+        bool fwd = dir > 0;
+        int tL = fwd ? -1 : nlev, ts = -1;
+        next_task(soff, nlev, dir, wave, tL, ts);
+        tL = __builtin_amdgcn_readfirstlane(tL);
+        ts = __builtin_amdgcn_readfirstlane(ts);
+        Row<T> cur, nxt;
+        if (fwd) fetch_row<T, true>(cur, A, ts, lane);
+        else fetch_row<T, false>(cur, A, ts, lane);
+        for (int L = fwd ? 0 : nlev - 1; fwd ? L < nlev : L >= 0; L += dir) {
+            while (tL == L) {
+                int nL = tL, ns = ts;
+                next_task(soff, nlev, dir, wave, nL, ns);
+                nL = __builtin_amdgcn_readfirstlane(nL);
+                ns = __builtin_amdgcn_readfirstlane(ns);
+                T y0[MAXW], y1[MAXW];
+#pragma unroll
+                for (int e = 0; e < MAXW; e++) {
+                    // a column outside y (never produced by the set-up)
+                    // is read as the row itself rather than out of bounds
+                    long q = e < cur.n ? cur.col[e] : cur.p;
+                    q = (unsigned long)q < (unsigned long)A.mtot ? q : (long)cur.p;
+                    y0[e] = A.y[2 * q];
+                    y1[e] = A.y[2 * q + 1];
+                }
+                if (fwd) fetch_row<T, true>(nxt, A, ns, lane);
+                else fetch_row<T, false>(nxt, A, ns, lane);
+                T t0, t1;
+                if (fwd) {
+                    row_update(cur, y0, y1, A.lcol, A.lval, A.y, A.mtot, t0, t1);
+                    if (cur.valid) {
+                        A.y[2 * (long)cur.p] = t0;
+                        A.y[2 * (long)cur.p + 1] = t1;
+                    }
+                } else {
+                    row_update(cur, y0, y1, A.ucol, A.uval, A.y, A.mtot, t0, t1);
+                    if (cur.valid) {
+                        A.y[2 * (long)cur.p] = cur.d[0] * t0 + cur.d[1] * t1;
+                        A.y[2 * (long)cur.p + 1] = cur.d[2] * t0 + cur.d[3] * t1;
+                    }
+                }
+                cur = nxt;
+                tL = nL;
+                ts = ns;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ----------------------------------------------------------------- set-up
+int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
+    R2P_TRY(r2p_ras_static(P, s));
+    r2p_jacobian *J = P->J;
+    r2p_model *m = J->m;
+    const Phys &ph = m->ph;
+    RasStatic &S = P->rs;
+    RasDyn &D = P->rd;
+    int mtot = S.mtot, ns = S.ns, order = P->o.order;
+    R2P_TRY(D.lev.ensure(mtot));
+    R2P_TRY(D.nlnat.ensure(mtot));
+    R2P_TRY(D.nunat.ensure(mtot));
+    R2P_TRY(D.pos.ensure(mtot));
+    R2P_TRY(D.perm.ensure(mtot));
+    R2P_TRY(D.glob.ensure(mtot));
+    R2P_TRY(D.owned.ensure(mtot));
+    R2P_TRY(D.nl.ensure(mtot));
+    R2P_TRY(D.nu.ensure(mtot));
+    R2P_TRY(D.sl_of.ensure(mtot));
+    R2P_TRY(D.dsrc_pos.ensure(mtot));
+    R2P_TRY(D.counters.ensure(64 + 2 * ns));
+    R2P_TRY(P->pin.ensure(1 << 16));
+    int nb = r2p_blocks(mtot, BS);
+    // 1. levels of the dependency graph
+    R2P_HIP(hipMemsetAsync(D.lev.p, 0, sizeof(int) * mtot, s));
+    int *changed = D.counters.p;
+    int *hflag = (int *)P->pin.p;
+    for (int it = 0; it < mtot + 2; it += 8) {
+        R2P_HIP(hipMemsetAsync(changed, 0, sizeof(int), s));
+        for (int k = 0; k < 8; k++) {
+            k_levels<<<nb, BS, 0, s>>>(mtot, ph.n, order, J->phi_o.p, S.glob_nat.p, S.aptr.p,
+                                       S.adj.p, D.lev.p, changed);
+            R2P_LAUNCH();
+        }
+        R2P_HIP(hipMemcpyAsync(hflag, changed, sizeof(int), hipMemcpyDeviceToHost, s));
+        R2P_HIP(hipStreamSynchronize(s));
+        if (*hflag == 0) break;
+    }
+    k_pred_count<<<nb, BS, 0, s>>>(mtot, ph.n, order, J->phi_o.p, S.glob_nat.p, S.aptr.p, S.adj.p,
+                                   D.nlnat.p, D.nunat.p);
+    R2P_LAUNCH();
+    // 2. level segments
+    int *dmax = D.counters.p + 64;
+    R2P_HIP(hipMemsetAsync(dmax, 0, sizeof(int) * ns, s));
+    k_sub_maxlev<<<nb, BS, 0, s>>>(mtot, ns, S.sub_of.p, D.lev.p, dmax);
+    R2P_LAUNCH();
+    R2P_HIP(hipMemcpyAsync(hflag, dmax, sizeof(int) * ns, hipMemcpyDeviceToHost, s));
+    R2P_HIP(hipStreamSynchronize(s));
+    D.h_nlev.assign(ns, 0);
+    D.h_lbase.assign(ns + 1, 0);
+    for (int t = 0; t < ns; t++) {
+        int cnt = S.h_off[t + 1] - S.h_off[t];
+        D.h_nlev[t] = cnt > 0 ? hflag[t] + 1 : 0;
+        if (D.h_nlev[t] > MAXLEV) {
+            r2p_set_error("subdomain %d has %d dependency levels (limit %d)", t, D.h_nlev[t], MAXLEV);
+            return R2P_EINVAL;
+        }
+        D.h_lbase[t + 1] = D.h_lbase[t] + D.h_nlev[t];
+    }
+    int nseg = D.h_lbase[ns];
+    D.nseg = nseg;
+    R2P_TRY(D.lptr_dev.ensure(nseg + 1));
+    R2P_TRY(D.soff.ensure(nseg + 1));
+    R2P_TRY(D.sub_lbase.ensure(ns));
+    R2P_TRY(D.sub_nlev.ensure(ns));
+    R2P_HIP(hipMemcpyAsync(D.sub_lbase.p, D.h_lbase.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    R2P_HIP(hipMemcpyAsync(D.sub_nlev.p, D.h_nlev.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    R2P_HIP(hipMemsetAsync(D.lptr_dev.p, 0, sizeof(int) * (nseg + 1), s));
+    k_level_count<<<nb, BS, 0, s>>>(mtot, S.sub_of.p, D.lev.p, D.sub_lbase.p, D.lptr_dev.p);
+    R2P_LAUNCH();
+    R2P_TRY(r2p_scan_int(D.lptr_dev.p, D.lptr_dev.p, nseg + 1, nullptr, P->iscratch, P->pin, s));
+    // 3. positions: stable sort by (level segment, descending predecessor count)
+    {
+        DBuf<unsigned> key, val, kt, vt;
+        DBuf<int> hist;
+        R2P_TRY(key.ensure(mtot));
+        R2P_TRY(val.ensure(mtot));
+        R2P_TRY(kt.ensure(mtot));
+        R2P_TRY(vt.ensure(mtot));
+        k_order_keys<<<nb, BS, 0, s>>>(mtot, S.sub_of.p, D.lev.p, D.sub_lbase.p, D.nlnat.p, key.p, val.p);
+        R2P_LAUNCH();
+        R2P_TRY(r2p_sort_pairs(key.p, val.p, kt.p, vt.p, mtot, r2p_bits_for(nseg) + 3, hist,
+                               P->iscratch, P->pin, s));
+        k_perm_gather<<<nb, BS, 0, s>>>(mtot, val.p, S.glob_nat.p, S.owned_nat.p, D.nlnat.p,
+                                        D.nunat.p, S.dsrc.p, D.pos.p, D.perm.p, D.glob.p,
+                                        D.owned.p, D.nl.p, D.nu.p, D.dsrc_pos.p);
+        R2P_LAUNCH();
+        R2P_HIP(hipStreamSynchronize(s));
+    }
+    // 4. slices of 64 rows per level, entry bases
+    k_slice_count<<<r2p_blocks(nseg + 1, BS), BS, 0, s>>>(nseg, D.lptr_dev.p, D.soff.p);
+    R2P_LAUNCH();
+    int nslice = 0;
+    R2P_TRY(r2p_scan_int(D.soff.p, D.soff.p, nseg + 1, &nslice, P->iscratch, P->pin, s));
+    D.nslice = nslice;
+    R2P_TRY(D.sl_start.ensure(nslice));
+    R2P_TRY(D.sl_cnt.ensure(nslice));
+    R2P_TRY(D.sl_wl.ensure(nslice));
+    R2P_TRY(D.sl_wu.ensure(nslice));
+    R2P_TRY(D.sl_bl.ensure(nslice + 1));
+    R2P_TRY(D.sl_bu.ensure(nslice + 1));
+    k_slice_fill<<<nseg, 64, 0, s>>>(nseg, D.lptr_dev.p, D.soff.p, nslice, D.nl.p, D.nu.p,
+                                     D.sl_start.p, D.sl_cnt.p, D.sl_wl.p, D.sl_wu.p, D.sl_of.p);
+    R2P_LAUNCH();
+    k_slice_size<<<r2p_blocks(nslice + 1, BS), BS, 0, s>>>(nslice, D.sl_wl.p, D.sl_bl.p);
+    R2P_LAUNCH();
+    k_slice_size<<<r2p_blocks(nslice + 1, BS), BS, 0, s>>>(nslice, D.sl_wu.p, D.sl_bu.p);
+    R2P_LAUNCH();
+    int nle = 0, nue = 0;
+    R2P_TRY(r2p_scan_int(D.sl_bl.p, D.sl_bl.p, nslice + 1, &nle, P->iscratch, P->pin, s));
+    R2P_TRY(r2p_scan_int(D.sl_bu.p, D.sl_bu.p, nslice + 1, &nue, P->iscratch, P->pin, s));
+    D.nlent = nle;
+    D.nuent = nue;
+    // RAS_SLICE entries of padding after each array: an empty last slice is
+    // still read (and ignored) by the sweep
+    R2P_TRY(D.lcol.ensure(nle + RAS_SLICE));
+    R2P_TRY(D.ucol.ensure(nue + RAS_SLICE));
+    R2P_TRY(D.lsrc.ensure(nle));
+    R2P_TRY(D.usrc.ensure(nue));
+    R2P_HIP(hipMemsetAsync(D.lcol.p, 0xff, sizeof(int) * (size_t)(nle + RAS_SLICE), s));
+    R2P_HIP(hipMemsetAsync(D.ucol.p, 0xff, sizeof(int) * (size_t)(nue + RAS_SLICE), s));
+    k_fill_entries<<<nb, BS, 0, s>>>(mtot, ph.n, order, J->phi_o.p, D.perm.p, S.glob_nat.p,
+                                     S.aptr.p, S.adj.p, S.asrc.p, D.pos.p, D.glob.p, D.sl_of.p,
+                                     D.sl_start.p, D.sl_bl.p, D.sl_bu.p, D.lcol.p, D.lsrc.p,
+                                     D.ucol.p, D.usrc.p);
+    R2P_LAUNCH();
+    // 5. numeric factorisation in FP64
+    R2P_TRY(D.f64.lval.ensure(4L * (nle + RAS_SLICE)));
+    R2P_TRY(D.f64.uval.ensure(4L * (nue + RAS_SLICE)));
+    R2P_TRY(D.f64.dinv.ensure(4L * mtot));
+    // padding slots stay zero (they are loaded, never used)
+    R2P_HIP(hipMemsetAsync(D.f64.lval.p, 0, sizeof(double) * 4 * (size_t)(nle + RAS_SLICE), s));
+    R2P_HIP(hipMemsetAsync(D.f64.uval.p, 0, sizeof(double) * 4 * (size_t)(nue + RAS_SLICE), s));
+    R2P_TRY(P->status.ensure(4));
+    R2P_HIP(hipMemsetAsync(P->status.p, 0, sizeof(int), s));
+    FactArgs F;
+    F.B.vp = J->vp.p; F.B.vs = J->vs.p; F.B.cw = J->cw.p; F.B.wc = J->wc.p; F.B.wd = J->wd.p;
+    F.B.nperf = ph.nperf;
+    F.lbase = D.sub_lbase.p; F.nlev = D.sub_nlev.p; F.soff = D.soff.p;
+    F.sl_st = D.sl_start.p; F.sl_cn = D.sl_cnt.p; F.sl_bl = D.sl_bl.p; F.sl_bu = D.sl_bu.p;
+    F.sl_of = D.sl_of.p; F.nl = D.nl.p; F.nu = D.nu.p; F.dsrc = D.dsrc_pos.p;
+    F.lcol = D.lcol.p; F.ucol = D.ucol.p; F.lsrc = D.lsrc.p; F.usrc = D.usrc.p;
+    F.lval = D.f64.lval.p; F.uval = D.f64.uval.p; F.dinv = D.f64.dinv.p; F.status = P->status.p;
+    k_bilu0<<<ns, WG, 0, s>>>(F);
+    R2P_LAUNCH();
+    if (P->o.precision == R2P_FP32) {
+        long nlp = 4L * (nle + RAS_SLICE), nup = 4L * (nue + RAS_SLICE);
+        R2P_TRY(D.f32.lval.ensure(nlp));
+        R2P_TRY(D.f32.uval.ensure(nup));
+        R2P_TRY(D.f32.dinv.ensure(4L * mtot));
+        k_cast<float><<<r2p_blocks(nlp, BS), BS, 0, s>>>(nlp, D.f64.lval.p, D.f32.lval.p);
+        R2P_LAUNCH();
+        k_cast<float><<<r2p_blocks(nup, BS), BS, 0, s>>>(nup, D.f64.uval.p, D.f32.uval.p);
+        R2P_LAUNCH();
+        k_cast<float><<<r2p_blocks(4L * mtot, BS), BS, 0, s>>>(4L * mtot, D.f64.dinv.p, D.f32.dinv.p);
+        R2P_LAUNCH();
+        R2P_TRY(P->t_rasf.ensure(2L * mtot));
+        R2P_TRY(P->t_rlf.ensure(2L * mtot));
+        R2P_HIP(hipMemsetAsync(P->t_rasf.p, 0, sizeof(float) * 2 * (size_t)mtot, s));
+    } else {
+        R2P_TRY(P->t_ras.ensure(2L * mtot));
+        R2P_TRY(P->t_rl.ensure(2L * mtot));
+        R2P_HIP(hipMemsetAsync(P->t_ras.p, 0, sizeof(double) * 2 * (size_t)mtot, s));
+    }
+    R2P_HIP(hipMemcpyAsync(hflag, P->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    R2P_HIP(hipStreamSynchronize(s));
+    if (*hflag) { r2p_set_error("singular diagonal block in block ILU(0)"); return R2P_ESINGULAR; }
+    D.maxlev = 0;
+    for (int t = 0; t < ns; t++) D.maxlev = std::max(D.maxlev, D.h_nlev[t]);
+    return 0;
+}
+
+template <class T>
+static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *xp,
+                       int accumulate, T *y, T *rl, const RasFactors<T> &F, hipStream_t s) {
+    RasDyn &D = P->rd;
+    int mtot = P->rs.mtot;
+    int nb = r2p_blocks(mtot, BS);
+    k_ras_gather<T><<<nb, BS, 0, s>>>(mtot, D.glob.p, r, rl);
+    R2P_LAUNCH();
+    SweepArgs<T> A;
+    A.lbase = D.sub_lbase.p; A.nlev = D.sub_nlev.p; A.soff = D.soff.p;
+    A.sl_st = D.sl_start.p; A.sl_cn = D.sl_cnt.p; A.sl_bl = D.sl_bl.p; A.sl_bu = D.sl_bu.p;
+    A.sl_wl = D.sl_wl.p; A.sl_wu = D.sl_wu.p;
+    A.nl = D.nl.p; A.nu = D.nu.p; A.lcol = D.lcol.p; A.ucol = D.ucol.p;
+    A.lval = F.lval.p; A.uval = F.uval.p; A.dinv = F.dinv.p; A.rl = rl; A.y = y;
+    A.mtot = mtot;
+    k_ras_sweep<T><<<P->rs.ns, WG, 0, s>>>(A);
+    R2P_LAUNCH();
+    k_ras_scatter<T><<<nb, BS, 0, s>>>(mtot, P->J->m->ph.n, D.glob.p, D.owned.p, y, xp,
+                                       accumulate, out);
+    R2P_LAUNCH();
+    return 0;
+}
+
+int r2p_ras_solve(r2p_cpr *P, const double *r, double *out, const double *xp, int accumulate,
+                  hipStream_t s) {
+    if (P->o.precision == R2P_FP32)
+        return ras_solve_t<float>(P, r, out, xp, accumulate, P->t_rasf.p, P->t_rlf.p, P->rd.f32, s);
+    return ras_solve_t<double>(P, r, out, xp, accumulate, P->t_ras.p, P->t_rl.p, P->rd.f64, s);
+}
+
+// --------------------------------------------------------------- export
+extern "C" int r2p_ras_info(r2p_cpr *P, int sub, int *nsub, int *m, int *nblk, int *nlevels) {
+    if (!P || !P->ready) { r2p_set_error("CPR not set up"); return R2P_ESTATE; }
+    if (nsub) *nsub = P->rs.ns;
+    if (sub < 0 || sub >= P->rs.ns) return 0;
+    int a = P->rs.h_off[sub], b = P->rs.h_off[sub + 1];
+    if (m) *m = b - a;
+    if (nlevels) *nlevels = P->rd.h_nlev[sub];
+    if (nblk) {
+        std::vector<int> nl(b - a), nu(b - a);
+        R2P_HIP(hipMemcpy(nl.data(), P->rd.nl.p + a, sizeof(int) * (b - a), hipMemcpyDeviceToHost));
+        R2P_HIP(hipMemcpy(nu.data(), P->rd.nu.p + a, sizeof(int) * (b - a), hipMemcpyDeviceToHost));
+        long t = 0;
+        for (int i = 0; i < b - a; i++) t += nl[i] + nu[i];
+        *nblk = (int)t;
+    }
+    return 0;
+}
+
+extern "C" int r2p_ras_export(r2p_cpr *P, int sub, int *glob, int *level, unsigned char *owned,
+                              double *dinv, int *erow, int *ecol, double *eval, void *stream) {
+    if (!P || !P->ready) { r2p_set_error("CPR not set up"); return R2P_ESTATE; }
+    if (sub < 0 || sub >= P->rs.ns) { r2p_set_error("bad subdomain"); return R2P_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    R2P_HIP(hipStreamSynchronize(s));
+    RasDyn &D = P->rd;
+    int mtot = P->rs.mtot, a = P->rs.h_off[sub], b = P->rs.h_off[sub + 1], m = b - a;
+    auto pull = [&](const auto *src, size_t cnt, auto &dst) -> int {
+        dst.resize(cnt);
+        if (cnt) {
+            hipError_t e = hipMemcpy(dst.data(), src, sizeof(dst[0]) * cnt, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return r2p_hip_fail(e, "export", __FILE__, __LINE__);
+        }
+        return 0;
+    };
+    std::vector<int> g, pm, lv, nl, nu, slof, slst, slbl, slbu, lc, uc;
+    std::vector<unsigned char> ow;
+    std::vector<double> lvv, uvv, dv;
+    R2P_TRY(pull(D.glob.p, mtot, g));
+    R2P_TRY(pull(D.perm.p, mtot, pm));
+    R2P_TRY(pull(D.lev.p, mtot, lv));
+    R2P_TRY(pull(D.nl.p, mtot, nl));
+    R2P_TRY(pull(D.nu.p, mtot, nu));
+    R2P_TRY(pull(D.sl_of.p, mtot, slof));
+    R2P_TRY(pull(D.sl_start.p, D.nslice, slst));
+    R2P_TRY(pull(D.sl_bl.p, D.nslice, slbl));
+    R2P_TRY(pull(D.sl_bu.p, D.nslice, slbu));
+    R2P_TRY(pull(D.lcol.p, D.nlent, lc));
+    R2P_TRY(pull(D.ucol.p, D.nuent, uc));
+    R2P_TRY(pull(D.f64.lval.p, 4L * D.nlent, lvv));
+    R2P_TRY(pull(D.f64.uval.p, 4L * D.nuent, uvv));
+    R2P_TRY(pull(D.f64.dinv.p, 4L * mtot, dv));
+    R2P_TRY(pull(D.owned.p, mtot, ow));
+    long k = 0;
+    for (int p = a; p < b; p++) {
+        int i = p - a;
+        if (glob) glob[i] = g[p];
+        if (level) level[i] = lv[pm[p]];
+        if (owned) owned[i] = ow[p];
+        if (dinv) memcpy(dinv + 4L * i, dv.data() + 4L * p, 4 * sizeof(double));
+        int sl = slof[p], lane = p - slst[sl];
+        for (int part = 0; part < 2; part++) {
+            int cnt = part == 0 ? nl[p] : nu[p];
+            long base = (part == 0 ? slbl[sl] : slbu[sl]) + lane;
+            const std::vector<int> &cc = part == 0 ? lc : uc;
+            const std::vector<double> &vv = part == 0 ? lvv : uvv;
+            for (int e = 0; e < cnt; e++, k++) {
+                long idx = base + (long)e * RAS_SLICE;
+                if (erow) erow[k] = g[p];
+                if (ecol) ecol[k] = g[cc[idx]];
+                if (eval) memcpy(eval + 4 * k, vv.data() + 4 * idx, 4 * sizeof(double));
+            }
+        }
+    }
+    (void)m;
+    return 0;
+}
