@@ -1,32 +1,46 @@
 """Benchmark of the Newton-step CPR-FGMRES path on one MI355X.
 
-A step is one implicit time step of the 200x200x50 (2,000,000-cell)
-correlated-permeability model with 25 wells: Newton iterations, each with
-assembly, decoupling, potential reordering, block ILU(0)/RAS set-up, AMG
-set-up, a CPR-FGMRES(30) solve to 1e-8 and the update.  All inputs are
-seeded and synthetic and resident in HBM before the timed region.
+Workload: the 200x200x50 (2,000,000-cell) correlated-permeability model with
+25 wells, seeded and synthetic, resident in HBM before any timed region.
 
-Prints one JSON line.  `value` is the mean wall time of one CPR-FGMRES solve
-(set-up excluded) in ms; `ms_per_step` the mean time-step wall time.  The
-roofline object prices the dominant kernel (the RAS triangular solve) by its
-algorithmic bytes per launch over its event-timed duration; cpu_baseline is
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+A step is one implicit time step: Newton iterations, each with assembly,
+decoupling, potential reordering, block ILU(0)/RAS set-up, AMG set-up, a
+CPR-FGMRES(30) solve to 1e-8 and the update.  From the cold start the step
+length follows a standard controller: it starts at 0.1 day, is halved when
+Newton fails (the state is left unchanged by the library) and doubled after a
+step that converged in at most 6 Newton iterations, up to the model's 10 days.
+The timed steps continue the same controller from the state the warm-up
+steps reached.
+
+Prints one JSON line on stdout (progress goes to stderr):
+  value            mean wall time of one CPR-FGMRES solve (r2p_solve, per
+                   Newton linear system, CPR set-up excluded) in ms;
+  ms_per_step      mean wall time of one time step (plain FP64);
+  fp32             the same steps with the FP32 preconditioner (FP64 FGMRES),
+                   with the field difference against the FP64 run;
+  roofline         the RAS apply (gather + level-scheduled triangular sweeps +
+                   restricted scatter, the largest single kernel of a solve):
+                   algorithmic bytes per apply over its HIP-event-timed mean
+                   duration on the library's stream, against 8 TB/s;
+  cpu_baseline     the FP64 CPU oracle, single-threaded, on a bounded sample
+                   of the same workload, scaled to the GPU's iterations.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import os
 import sys
 import time
-
-import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "CPR-GMRES solve ms + HBM GB/s at 2M cells; step time plain vs FP32+learned"
 HBM_PEAK_GBS = 8000.0
+DT_INIT, DT_MIN = 0.1, 1e-4
+GROW_ITS = 6
 
 
 def log(*a):
@@ -34,33 +48,42 @@ def log(*a):
 
 
 def ras_bytes(P, model, prec_bytes):
-    """Algorithmic bytes of one RAS apply (forward + backward sweeps with the
-    gather and restricted scatter): every factor block and inverse diagonal
-    read once, column/row index data read once, the residual gathered once
-    per local row, the local vector written and read twice, the owned rows
-    written once."""
+    """Algorithmic bytes of one RAS apply.
+
+    Per local row of every overlapped subdomain: its off-diagonal factor blocks
+    (4 values + a column index each) and its inverse diagonal block read once;
+    its row lengths and gather index read once; the gathered right-hand side
+    read from the global vector (16 B) and written locally; the local vector
+    written by the forward sweep, read and rewritten by the backward sweep,
+    read by the scatter; the owned flag read once.  The owned rows' results
+    (N doubles) are written once.  Neighbour values re-read within a sweep are
+    not counted (they are the same bytes)."""
     from paper_1701_06254_amd import r2p
     ns = P.ras_info()
     m_tot = nblk = 0
     for s in range(ns):
-        import ctypes as C
         a, m, nb, nl = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         r2p.load().r2p_ras_info(P.h, s, C.byref(a), C.byref(m), C.byref(nb), C.byref(nl))
         m_tot += m.value
         nblk += nb.value
-    N = model.N
-    factors = (4 * prec_bytes) * (nblk + m_tot)           # L/U blocks + inverse diagonals
-    index = 4 * nblk + (4 + 4 + 4 + 1) * m_tot             # ecol; glob, eptr, nl, owned
-    vectors = 16 * m_tot + 2 * 2 * (2 * prec_bytes) * m_tot + 8 * N
-    return factors + index + vectors, m_tot, nblk
+    vb = 2 * prec_bytes                       # one local 2-vector entry
+    factors = 4 * prec_bytes * (nblk + m_tot) + 4 * nblk
+    per_row = 4 + 4 + 4 + 1                   # n_L, n_U, gather index, owned flag
+    vectors = 16 + vb + vb + 2 * vb + vb      # gather read/write, fwd write, bwd read+write, scatter read
+    return factors + per_row * m_tot + vectors * m_tot + 8 * model.N, m_tot, nblk
 
 
 def spmv_bytes(model):
+    """Algorithmic bytes of y = J x: 7 stencil blocks (32 B) per cell, x and
+    y (16 B each) per cell, and per perforation / well the coupling blocks,
+    offsets and vector entries."""
     n, nw, nperf = model.n, model.nw, model.nperf
-    return 7 * 32 * n + 4 * n + 16 * n + 16 * n + nperf * (16 + 16 + 4 + 4) + nw * (8 + 32)
+    return 7 * 32 * n + 16 * n + 16 * n + nperf * (32 + 32 + 4) + nw * (32 + 8 + 16 + 16)
 
 
-def time_kernel(fn, reps):
+def time_on_stream(fn, reps):
+    """Mean ms of fn() over reps calls, from HIP events on the current stream
+    (the stream every library call is enqueued on)."""
     import torch
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -73,15 +96,52 @@ def time_kernel(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(w, gpu_solve_its, sample_its=5):
-    """FP64 oracle on a bounded sample of the same workload: CPR set-up plus
-    `sample_its` FGMRES iterations on the first Newton system of the first
-    step; scaled to one solve with the GPU's iteration count."""
+def run_steps(model, x, dt, nsteps, opts, dt_max, tag, dts=None):
+    """nsteps accepted implicit steps on x (in place).  With `dts` given the
+    step lengths are replayed instead of controlled.  Returns the next step
+    length and one record per attempted Newton step."""
+    recs = []
+    for k in range(nsteps):
+        if dts is not None:
+            dt = dts[k]
+        while True:
+            info = model.newton_step(x, dt, opts)
+            recs.append(dict(dt=dt, status=info.status, newton=info.newton_its,
+                             linear=info.linear_its, ms_setup=info.ms_setup,
+                             ms_solve=info.ms_solve, ms_assemble=info.ms_assemble,
+                             ms_total=info.ms_total))
+            log(f"{tag} step {k}: dt {dt:.4g} d status {info.status} newton {info.newton_its} "
+                f"linear {info.linear_its} setup {info.ms_setup:.0f} solve {info.ms_solve:.0f} "
+                f"total {info.ms_total:.0f} ms")
+            if info.status == 0:
+                break
+            dt *= 0.5
+            if dt < DT_MIN:
+                raise RuntimeError("time step fell below the minimum")
+        if dts is None and info.newton_its <= GROW_ITS:
+            dt = min(2.0 * dt, dt_max)
+    return dt, recs
+
+
+def summarise(recs):
+    solves = sum(r["newton"] for r in recs)
+    lin = sum(r["linear"] for r in recs)
+    return dict(solves=solves, linear_its=lin,
+                solve_ms=sum(r["ms_solve"] for r in recs) / max(solves, 1),
+                setup_ms=sum(r["ms_setup"] for r in recs) / max(solves, 1),
+                its_per_solve=lin / max(solves, 1))
+
+
+def cpu_baseline(w, gpu_its_per_solve, dt, sample_its):
+    """FP64 oracle, single-threaded, on the first Newton system of the cold
+    start at the controller's first step length: CPR set-up (reported, not in
+    value) and `sample_its` FGMRES iterations, whose mean iteration time is
+    scaled to the GPU's mean iterations per solve."""
     import oracle
     oracle.build(force=False)
     m = oracle.Model(w)
     x = m.initial_state()
-    J, F = m.jacobian(x, x, w["dt"])
+    J, F = m.jacobian(x, x, dt)
     t0 = time.perf_counter()
     Ad, bd = oracle.decouple(J, -F, m.n, oracle.DEC_QI)
     P = oracle.Cpr(Ad, m, x, oracle.cpr_opts())
@@ -89,12 +149,12 @@ def cpu_baseline(w, gpu_solve_its, sample_its=5):
     y, st, its, rr = oracle.fgmres(Ad, bd, P, maxit=sample_its)
     t2 = time.perf_counter()
     per_it = (t2 - t1) / max(its, 1)
-    solve_ms = per_it * gpu_solve_its * 1e3
-    return dict(value=round(solve_ms, 1), unit="ms", cores=1, kind="oracle",
-                sample=f"FP64 oracle, first Newton system of the 2M-cell model: CPR set-up "
-                       f"{(t1 - t0):.1f} s (not in value) and {its} FGMRES(30) iterations "
-                       f"({per_it * 1e3:.0f} ms each), scaled to the {gpu_solve_its:.1f} "
-                       f"iterations of the mean GPU solve", setup_s=round(t1 - t0, 2))
+    return dict(value=round(per_it * gpu_its_per_solve * 1e3, 1), unit="ms", cores=1,
+                kind="oracle",
+                sample=f"FP64 oracle, one thread: first Newton system of the 2M-cell cold "
+                       f"start (dt {dt} d), decoupling + CPR set-up {t1 - t0:.2f} s (not in "
+                       f"value) and {its} FGMRES(30) iterations at {per_it * 1e3:.0f} ms each, "
+                       f"scaled to the {gpu_its_per_solve:.1f} iterations of the mean GPU solve")
 
 
 def main():
@@ -103,14 +163,14 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--form", choices=["two-stage", "fpf"], default="two-stage")
-    ap.add_argument("--agg-passes", type=int, default=2)
+    ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-its", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "decomposition is not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): this build has no "
+              "multi-GPU decomposition", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -121,47 +181,54 @@ def main():
     log(f"workload {w['name']}: {w['grid']['n']} cells, {len(w['wells'])} wells")
     model = r2p.Model(w)
     x = model.initial_state()
-    prec = r2p.FP32 if args.precision == "fp32" else r2p.FP64
     form = r2p.CPR_FPF if args.form == "fpf" else r2p.CPR_TWO_STAGE
-    opts = r2p.newton_opts(cpr=r2p.cpr_opts(precision=prec, form=form,
-                                             agg_passes=args.agg_passes))
-    for k in range(args.warmup):
-        info = model.newton_step(x, w["dt"], opts)
-        log(f"warmup step {k}: status {info.status} newton {info.newton_its} linear "
-            f"{info.linear_its} {info.ms_total:.1f} ms")
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        info = model.newton_step(x, w["dt"], opts)
-        infos.append(info)
-        log(f"step {k}: status {info.status} newton {info.newton_its} linear {info.linear_its} "
-            f"assemble {info.ms_assemble:.1f} setup {info.ms_setup:.1f} solve "
-            f"{info.ms_solve:.1f} total {info.ms_total:.1f} ms")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    n_solves = sum(i.newton_its for i in infos)
-    lin_its = sum(i.linear_its for i in infos)
-    solve_ms = sum(i.ms_solve for i in infos) / max(n_solves, 1)
-    setup_ms = sum(i.ms_setup for i in infos) / max(n_solves, 1)
-    asm_ms = sum(i.ms_assemble for i in infos) / max(sum(i.newton_its + 1 for i in infos), 1)
-    its_per_solve = lin_its / max(n_solves, 1)
+    o64 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form))
+    o32 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, precision=r2p.FP32))
+    dt_max = float(w["dt"])
 
-    # kernel timing on the current state's system
+    dt, _ = run_steps(model, x, DT_INIT, args.warmup, o64, dt_max, "warmup")
+    x0 = x.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dt_next, recs = run_steps(model, x, dt, args.steps, o64, dt_max, "fp64")
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    s64 = summarise(recs)
+    accepted = [r["dt"] for r in recs if r["status"] == 0]
+
+    fp32 = None
+    if not args.no_fp32:
+        x32 = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, recs32 = run_steps(model, x32, dt, args.steps, o32, dt_max, "fp32", dts=accepted)
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t0) * 1e3 / args.steps
+        s32 = summarise(recs32)
+        p64, s_64 = x[0:2 * model.n:2], x[1:2 * model.n:2]
+        p32, s_32 = x32[0:2 * model.n:2], x32[1:2 * model.n:2]
+        fp32 = dict(ms_per_step=round(ms32, 3), solve_ms=round(s32["solve_ms"], 3),
+                    setup_ms=round(s32["setup_ms"], 3),
+                    linear_its_per_solve=round(s32["its_per_solve"], 2),
+                    newton_its=s32["solves"],
+                    rel_err_p=float(torch.linalg.norm(p32 - p64) / torch.linalg.norm(p64)),
+                    rel_err_sw=float(torch.linalg.norm(s_32 - s_64) /
+                                     max(float(torch.linalg.norm(s_64)), 1e-300)),
+                    learned_warm_start=None)
+
+    # per-kernel timing on the last state's first Newton system
     J = r2p.Jacobian(model)
-    b = J.assemble(x, x, w["dt"])
-    P = r2p.Cpr().setup(J, opts.cpr)
+    J.assemble(x, x, dt_next)
+    P = r2p.Cpr().setup(J, o64.cpr)
     v = torch.randn(model.N, dtype=torch.float64, device="cuda")
     y = torch.empty_like(v)
     fp = torch.randn(model.n, dtype=torch.float64, device="cuda")
     xp = torch.empty_like(fp)
-    t_spmv = time_kernel(lambda: J.spmv(v, y), 50)
-    t_ras = time_kernel(lambda: P.ras_apply(v, y), 10)
-    t_amg = time_kernel(lambda: P.amg_vcycle(fp, xp), 10)
-    t_cpr = time_kernel(lambda: P.apply(v, y), 10)
-    pb = 4 if prec == r2p.FP32 else 8
-    rb, m_tot, nblk = ras_bytes(P, model, pb)
+    t_spmv = time_on_stream(lambda: J.spmv(v, y), 50)
+    t_ras = time_on_stream(lambda: P.ras_apply(v, y), 20)
+    t_amg = time_on_stream(lambda: P.amg_vcycle(fp, xp), 20)
+    t_cpr = time_on_stream(lambda: P.apply(v, y), 20)
+    rb, m_tot, nblk = ras_bytes(P, model, 8)
     sb = spmv_bytes(model)
     ras_gbs = rb / (t_ras * 1e-3) / 1e9
     spmv_gbs = sb / (t_spmv * 1e-3) / 1e9
@@ -169,29 +236,33 @@ def main():
         f"({ras_gbs:.0f} GB/s), vcycle {t_amg * 1e3:.1f} us, cpr {t_cpr * 1e3:.1f} us")
 
     out = {
-        "metric": METRIC, "value": round(solve_ms, 3), "unit": "ms", "n_gpus": 1,
+        "metric": METRIC, "value": round(s64["solve_ms"], 3), "unit": "ms", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if prec == r2p.FP64 else "f64+f32-preconditioner",
-        "data": "synthetic",
-        "config": {"workload": f"{w['name']} ({w['grid']['n']} cells, {len(w['wells'])} wells), "
-                               f"dt {w['dt']} d, CPR {args.form} QI + potential order, RAS 4x4 "
-                               f"overlap 1 BILU(0), aggregation AMG V(1,1), FGMRES(30) rtol 1e-8",
-                   "cells": w["grid"]["n"], "precision": args.precision, "form": args.form},
-        "newton_its_per_step": round(n_solves / args.steps, 2),
-        "linear_its_per_solve": round(its_per_solve, 2),
-        "setup_ms_per_newton": round(setup_ms, 3), "assemble_ms": round(asm_ms, 3),
-        "ms_per_fgmres_iteration": round(solve_ms / max(its_per_solve, 1e-9), 4),
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w['name']}: {w['grid']['n']} cells, {len(w['wells'])} wells, "
+                               f"adaptive dt from {DT_INIT} d (max {dt_max} d); CPR {args.form}, "
+                               "QI + local potential order, RAS 4x4 overlap 1 BILU(0), "
+                               "aggregation AMG V(1,1), FGMRES(30) rtol 1e-8",
+                   "cells": w["grid"]["n"], "form": args.form},
+        "dt_days": accepted,
+        "newton_its_per_step": round(s64["solves"] / args.steps, 2),
+        "linear_its_per_solve": round(s64["its_per_solve"], 2),
+        "setup_ms_per_solve": round(s64["setup_ms"], 3),
+        "ms_per_fgmres_iteration": round(s64["solve_ms"] / max(s64["its_per_solve"], 1e-9), 4),
         "kernels_us": {"spmv": round(t_spmv * 1e3, 2), "ras_apply": round(t_ras * 1e3, 2),
                        "amg_vcycle": round(t_amg * 1e3, 2), "cpr_apply": round(t_cpr * 1e3, 2)},
         "spmv_gbs": round(spmv_gbs, 1),
-        "roofline": {"bound": "hbm", "kernel": "k_ras_solve", "achieved": round(ras_gbs, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ras_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": rb},
+        "roofline": {"bound": "hbm", "kernel": "ras_apply (k_ras_gather+k_ras_sweep+k_ras_scatter)",
+                     "achieved": round(ras_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ras_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": rb, "local_rows": m_tot, "offdiag_blocks": nblk},
+        "fp32": fp32,
     }
     if not args.no_cpu_baseline:
         try:
-            out["cpu_baseline"] = cpu_baseline(w, its_per_solve)
+            out["cpu_baseline"] = cpu_baseline(w, s64["its_per_solve"], DT_INIT,
+                                               args.cpu_sample_its)
         except Exception as e:  # the baseline is reported, never required
             log(f"cpu baseline failed: {e}")
             out["cpu_baseline"] = None

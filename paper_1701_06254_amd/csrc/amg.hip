@@ -65,17 +65,22 @@ __global__ void k_app_v7(int n, const double2 *vp, double *v7) {
     if (t < 7L * n) v7[t] = vp[t].x;
 }
 
-// Next-level rows with more than BIG members are restricted by a wavefront.
+// Rows of a CSR-like structure longer than a threshold: next-level rows with
+// more than BIG members (restricted by a wavefront), and matrix rows with
+// more than HEAVY entries (smoothed by a wavefront).  Aggregates that
+// absorbed many unmatched rows make a few coarse rows hundreds of entries
+// long; one thread per row would serialise the whole launch on them.
 constexpr int BIG = 16;
-__global__ void k_big_flag(int nc, const int *mptr, int *flag) {
+constexpr int HEAVY = 32;
+__global__ void k_long_flag(int n, const int *ptr, int thr, int *flag) {
     int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I < nc) flag[I] = mptr[I + 1] - mptr[I] > BIG;
-    if (I == nc) flag[I] = 0;
+    if (I < n) flag[I] = ptr[I + 1] - ptr[I] > thr;
+    if (I == n) flag[I] = 0;
 }
 
-__global__ void k_big_list(int nc, const int *mptr, const int *scan, int *big) {
+__global__ void k_long_list(int n, const int *ptr, int thr, const int *scan, int *list) {
     int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I < nc && mptr[I + 1] - mptr[I] > BIG) big[scan[I]] = I;
+    if (I < n && ptr[I + 1] - ptr[I] > thr) list[scan[I]] = I;
 }
 
 // ------------------------------------------------------------- matching
@@ -415,6 +420,23 @@ static int aggregate_pass(r2p_cpr *P, int n, const int *rp, const int *col, cons
     return 0;
 }
 
+// List (ascending) of the rows i < n with ptr[i+1] - ptr[i] > thr.
+static int long_rows(r2p_cpr *P, int n, const int *ptr, int thr, DBuf<int> &list, int *count,
+                     hipStream_t s) {
+    DBuf<int> flag;
+    R2P_TRY(flag.ensure(n + 1));
+    k_long_flag<<<r2p_blocks(n + 1, BS), BS, 0, s>>>(n, ptr, thr, flag.p);
+    R2P_LAUNCH();
+    int cnt = 0;
+    R2P_TRY(r2p_scan_int(flag.p, flag.p, n + 1, &cnt, P->iscratch, P->pin, s));
+    R2P_TRY(list.ensure(cnt));
+    k_long_list<<<r2p_blocks(n, BS), BS, 0, s>>>(n, ptr, thr, flag.p, list.p);
+    R2P_LAUNCH();
+    R2P_HIP(hipStreamSynchronize(s));
+    *count = cnt;
+    return 0;
+}
+
 int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
     r2p_jacobian *J = P->J;
     const Phys &ph = J->m->ph;
@@ -481,19 +503,8 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
         C.n = nc;
         C.nnz = nnzc;
         R2P_TRY(build_members(P, A.n, A.agg.p, nc, A.mptr, A.mem, s));
-        {
-            DBuf<int> flag;
-            R2P_TRY(flag.ensure(nc + 1));
-            k_big_flag<<<r2p_blocks(nc + 1, BS), BS, 0, s>>>(nc, A.mptr.p, flag.p);
-            R2P_LAUNCH();
-            int nbig = 0;
-            R2P_TRY(r2p_scan_int(flag.p, flag.p, nc + 1, &nbig, P->iscratch, P->pin, s));
-            R2P_TRY(A.big.ensure(nbig));
-            k_big_list<<<r2p_blocks(nc, BS), BS, 0, s>>>(nc, A.mptr.p, flag.p, A.big.p);
-            R2P_LAUNCH();
-            R2P_HIP(hipStreamSynchronize(s));
-            A.nbig = nbig;
-        }
+        R2P_TRY(long_rows(P, nc, A.mptr.p, BIG, A.big, &A.nbig, s));
+        R2P_TRY(long_rows(P, nc, C.rp.p, HEAVY, C.heavy, &C.nheavy, s));
         l++;
     }
     P->nlev = l + 1;
@@ -542,31 +553,49 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
 // --------------------------------------------------------------- V-cycle
 template <class T>
 struct DownArgs {
-    int n;
+    int n, nbs;                  // rows; workgroups of the one-thread-per-row part
+    const int *heavy;            // rows longer than HEAVY, one wavefront each
+    int nheavy;
     const int *rp, *col;
     const T *val, *l1;
-    const T *b;                  // right-hand side of this level (or NULL: use f)
-    const double *f;             // level 0: Pi_r f read from the full vector
-    int fstride;
+    const T *b;                  // right-hand side of this level
     T *x;                        // pre-smoothed iterate of this level
     T *r;                        // its residual
 };
 
-// Pre-smoothing from a zero guess (x = b / d) and the residual r = b - A x,
-// one thread per row.
+// Pre-smoothing from a zero guess (x = b / d) and the residual r = b - A x.
+// The first nbs workgroups take one row per thread (entries in ascending
+// column order); rows longer than HEAVY are left to the trailing
+// workgroups, one wavefront per row (lanes stride over the entries, then a
+// fixed butterfly), so the sum order is fixed either way.
 template <class T>
 __global__ void k_down(DownArgs<T> A) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    T bi = A.f ? (T)A.f[(long)A.fstride * i] : A.b[i];
-    A.x[i] = bi / A.l1[i];
-    T r = bi;
-    for (int z = A.rp[i]; z < A.rp[i + 1]; z++) {
-        int j = A.col[z];
-        T bj = A.f ? (T)A.f[(long)A.fstride * j] : A.b[j];
-        r -= A.val[z] * (bj / A.l1[j]);
+    if ((int)blockIdx.x < A.nbs) {
+        int i = blockIdx.x * blockDim.x + threadIdx.x;
+        if (i >= A.n) return;
+        T bi = A.b[i];
+        A.x[i] = bi / A.l1[i];
+        int z0 = A.rp[i], z1 = A.rp[i + 1];
+        if (z1 - z0 > HEAVY) return;
+        T r = bi;
+        for (int z = z0; z < z1; z++) {
+            int j = A.col[z];
+            r -= A.val[z] * (A.b[j] / A.l1[j]);
+        }
+        A.r[i] = r;
+    } else {
+        int w = ((int)blockIdx.x - A.nbs) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        if (w >= A.nheavy) return;
+        int lane = threadIdx.x & 63;
+        int i = A.heavy[w];
+        T acc = (T)0;
+        for (int z = A.rp[i] + lane; z < A.rp[i + 1]; z += 64) {
+            int j = A.col[z];
+            acc += A.val[z] * (A.b[j] / A.l1[j]);
+        }
+        for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+        if (lane == 0) A.r[i] = A.b[i] - acc;
     }
-    A.r[i] = r;
 }
 
 // Restriction P^T r.  The first nbs workgroups give one thread per coarse
@@ -644,48 +673,80 @@ __global__ void k_up0(Level0<T> A, const int *agg, const T *x, const T *xc, doub
 
 template <class T>
 struct UpArgs {
-    int n;
+    int n, nbs;
+    const int *heavy;
+    int nheavy;
     const int *rp, *col, *agg;
     const T *val, *l1;
     const T *b;
-    const double *f;
-    int fstride;
     const T *x;                  // pre-smoothed iterate
     const T *xc;                 // coarse correction
     T *xo;                       // output (this level's result)
-    double *xod;                 // level 0: FP64 output
 };
 
-// Prolongation of the coarse correction and post-smoothing, one thread per
-// fine row: x' = x + P xc; x'' = x' + (b - A x') / d.
+// Prolongation of the coarse correction and post-smoothing of one fine row:
+// x' = x + P xc; x'' = x' + (b - A x') / d.  Rows are split between threads
+// and wavefronts as in k_down.
 template <class T>
 __global__ void k_up(UpArgs<T> A) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    T bi = A.f ? (T)A.f[(long)A.fstride * i] : A.b[i];
-    T r = bi;
-    for (int z = A.rp[i]; z < A.rp[i + 1]; z++) {
-        int j = A.col[z];
-        r -= A.val[z] * (A.x[j] + A.xc[A.agg[j]]);
+    if ((int)blockIdx.x < A.nbs) {
+        int i = blockIdx.x * blockDim.x + threadIdx.x;
+        if (i >= A.n) return;
+        int z0 = A.rp[i], z1 = A.rp[i + 1];
+        if (z1 - z0 > HEAVY) return;
+        T r = A.b[i];
+        for (int z = z0; z < z1; z++) {
+            int j = A.col[z];
+            r -= A.val[z] * (A.x[j] + A.xc[A.agg[j]]);
+        }
+        T xi = A.x[i] + A.xc[A.agg[i]];
+        A.xo[i] = xi + r / A.l1[i];
+    } else {
+        int w = ((int)blockIdx.x - A.nbs) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        if (w >= A.nheavy) return;
+        int lane = threadIdx.x & 63;
+        int i = A.heavy[w];
+        T acc = (T)0;
+        for (int z = A.rp[i] + lane; z < A.rp[i + 1]; z += 64) {
+            int j = A.col[z];
+            acc += A.val[z] * (A.x[j] + A.xc[A.agg[j]]);
+        }
+        for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+        if (lane == 0) {
+            T xi = A.x[i] + A.xc[A.agg[i]];
+            A.xo[i] = xi + (A.b[i] - acc) / A.l1[i];
+        }
     }
-    T xi = A.x[i] + A.xc[A.agg[i]];
-    T v = xi + r / A.l1[i];
-    if (A.xod) A.xod[i] = (double)v;
-    else A.xo[i] = v;
 }
 
+// Coarsest solve x = A_c^-1 b with the stored inverse (column-major, so a
+// column read by 64 lanes is contiguous).  A workgroup of CS_WAVES
+// wavefronts covers 64 rows; wavefront w sums its quarter of the columns,
+// then the quarters are added in wavefront order.
+constexpr int CS_WAVES = 4;
 template <class T>
-__global__ void k_coarse_solve(int n, const double *invT, const T *b, const double *f, int fstride,
-                               T *x, double *xd) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__global__ __launch_bounds__(64 * CS_WAVES) void k_coarse_solve(int n, const double *invT,
+                                                                const T *b, const double *f,
+                                                                int fstride, T *x, double *xd) {
+    __shared__ double part[CS_WAVES][64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int i = blockIdx.x * 64 + lane;
+    int q = (n + CS_WAVES - 1) / CS_WAVES;
+    int c0 = w * q, c1 = min(n, c0 + q);
+    int ii = i < n ? i : n - 1;
     double s = 0.0;
-    for (int c = 0; c < n; c++) {
+#pragma unroll 8
+    for (int c = c0; c < c1; c++) {
         double bc = f ? f[(long)fstride * c] : (double)b[c];
-        s += invT[(long)c * n + i] * bc;
+        s += invT[(long)c * n + ii] * bc;
     }
-    if (xd) xd[i] = s;
-    else x[i] = (T)s;
+    part[w][lane] = s;
+    __syncthreads();
+    if (w != 0 || i >= n) return;
+    double t = part[0][lane];
+    for (int k = 1; k < CS_WAVES; k++) t += part[k][lane];
+    if (xd) xd[i] = t;
+    else x[i] = (T)t;
 }
 
 template <class T>
@@ -708,8 +769,8 @@ static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStrea
     };
     if (nl == 1) {
         AmgLevel &C = P->lv[0];
-        k_coarse_solve<T><<<r2p_blocks(C.n, BS), BS, 0, s>>>(C.n, P->cinv.p, vb(C), f, fstride,
-                                                            vx(C), xp);
+        k_coarse_solve<T><<<r2p_blocks(C.n, 64), 64 * CS_WAVES, 0, s>>>(C.n, P->cinv.p, vb(C), f,
+                                                                       fstride, vx(C), xp);
         R2P_LAUNCH();
         return 0;
     }
@@ -728,13 +789,13 @@ static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStrea
             k_down0<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(Z, vx(A), vxo(A));
         } else {
             DownArgs<T> D;
-            D.n = A.n; D.rp = A.rp.p; D.col = A.col.p;
+            D.n = A.n; D.nbs = r2p_blocks(A.n, BS);
+            D.heavy = A.heavy.p; D.nheavy = A.nheavy;
+            D.rp = A.rp.p; D.col = A.col.p;
             D.val = vals(A); D.l1 = l1s(A);
             D.b = vb(A);
-            D.f = nullptr;
-            D.fstride = 1;
             D.x = vx(A); D.r = vxo(A);
-            k_down<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(D);
+            k_down<T><<<D.nbs + r2p_blocks(A.nheavy, BS / 64), BS, 0, s>>>(D);
         }
         R2P_LAUNCH();
         int nbs = r2p_blocks(C.n, BS);
@@ -743,8 +804,8 @@ static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStrea
         R2P_LAUNCH();
     }
     AmgLevel &Cst = P->lv[nl - 1];
-    k_coarse_solve<T><<<r2p_blocks(Cst.n, BS), BS, 0, s>>>(Cst.n, P->cinv.p, vb(Cst), nullptr, 1,
-                                                          vxo(Cst), nullptr);
+    k_coarse_solve<T><<<r2p_blocks(Cst.n, 64), 64 * CS_WAVES, 0, s>>>(Cst.n, P->cinv.p, vb(Cst),
+                                                                     nullptr, 1, vxo(Cst), nullptr);
     R2P_LAUNCH();
     for (int l = nl - 2; l >= 0; l--) {
         AmgLevel &A = P->lv[l];
@@ -755,14 +816,13 @@ static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStrea
             continue;
         }
         UpArgs<T> U;
-        U.n = A.n; U.rp = A.rp.p; U.col = A.col.p; U.agg = A.agg.p; U.val = vals(A); U.l1 = l1s(A);
-        U.b = l == 0 ? nullptr : vb(A);
-        U.f = l == 0 ? f : nullptr;
-        U.fstride = fstride;
+        U.n = A.n; U.nbs = r2p_blocks(A.n, BS);
+        U.heavy = A.heavy.p; U.nheavy = A.nheavy;
+        U.rp = A.rp.p; U.col = A.col.p; U.agg = A.agg.p; U.val = vals(A); U.l1 = l1s(A);
+        U.b = vb(A);
         U.x = vx(A); U.xc = vxo(C);
         U.xo = vxo(A);
-        U.xod = l == 0 ? xp : nullptr;
-        k_up<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(U);
+        k_up<T><<<U.nbs + r2p_blocks(A.nheavy, BS / 64), BS, 0, s>>>(U);
         R2P_LAUNCH();
     }
     return 0;

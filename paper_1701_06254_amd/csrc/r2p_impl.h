@@ -190,6 +190,8 @@ struct AmgLevel {
     DBuf<int> mptr, mem;     // next level's member lists (n_next+1, n)
     DBuf<int> big;           // next-level rows with many members (restricted by a wavefront)
     int nbig = 0;
+    DBuf<int> heavy;         // rows with many entries (smoothed by a wavefront)
+    int nheavy = 0;
     DBuf<double> v7;         // level 0 only: A_pp in the 7-slot stencil layout (slot-major)
     DBuf<float> v7f;
     AmgLevelT<float> f32;
@@ -206,7 +208,7 @@ struct r2p_cpr {
     int nlev = 0;
     AmgLevel lv[24];
     int ncoarse = 0;
-    DBuf<double> cinv;       // coarsest inverse, row-major
+    DBuf<double> cinv;       // coarsest inverse, column-major: cinv[c*n + i] = (A^-1)_ic
     DBuf<float> cinvf;
     DBuf<double> lu;         // coarsest dense LU scratch
     DBuf<int> piv;
