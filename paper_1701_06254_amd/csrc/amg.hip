@@ -330,8 +330,9 @@ __global__ __launch_bounds__(1024) void k_dense_lu_inv(int n, double *a, int *pi
 // Member lists (CSR, ascending) of the nc aggregates of agg[0..n).
 static int build_members(r2p_cpr *P, int n, const int *agg, int nc, DBuf<int> &mptr,
                          DBuf<int> &mem, hipStream_t s) {
-    DBuf<unsigned> key, kt, vt;
-    DBuf<int> hist;
+    SetupWork &W = P->ws;
+    DBuf<unsigned> &key = W.u[0], &kt = W.u[1], &vt = W.u[2];
+    DBuf<int> &hist = W.i[0];
     R2P_TRY(mptr.ensure(nc + 1));
     R2P_TRY(mem.ensure(n));
     R2P_TRY(key.ensure(n));
@@ -351,8 +352,10 @@ static int build_members(r2p_cpr *P, int n, const int *agg, int nc, DBuf<int> &m
 static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, const double *val,
                     const int *agg, int nc, DBuf<int> &rpc, DBuf<int> &colc, DBuf<double> &valc,
                     int *nnzc, hipStream_t s) {
-    DBuf<unsigned> keyI, keyJz, idx, kt, vt, keyIs;
-    DBuf<int> flag, hist;
+    SetupWork &W = P->ws;
+    DBuf<unsigned> &keyI = W.u[0], &keyJz = W.u[1], &keyIs = W.u[2], &idx = W.u[3], &kt = W.u[4],
+                   &vt = W.u[5];
+    DBuf<int> &flag = W.i[0], &hist = W.i[1];
     R2P_TRY(keyI.ensure(nnz));
     R2P_TRY(keyJz.ensure(nnz));
     R2P_TRY(keyIs.ensure(nnz));
@@ -389,8 +392,9 @@ static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, c
 // One aggregation pass: agg (row -> aggregate) and the aggregate count.
 static int aggregate_pass(r2p_cpr *P, int n, const int *rp, const int *col, const double *val,
                           DBuf<int> &agg, int *nc, hipStream_t s) {
-    DBuf<double> thr;
-    DBuf<int> match, prop, flag, jt;
+    SetupWork &W = P->ws;
+    DBuf<double> &thr = W.d[0];
+    DBuf<int> &match = W.i[0], &prop = W.i[1], &flag = W.i[2], &jt = W.i[3];
     R2P_TRY(thr.ensure(n));
     R2P_TRY(match.ensure(n));
     R2P_TRY(prop.ensure(n));
@@ -423,7 +427,7 @@ static int aggregate_pass(r2p_cpr *P, int n, const int *rp, const int *col, cons
 // List (ascending) of the rows i < n with ptr[i+1] - ptr[i] > thr.
 static int long_rows(r2p_cpr *P, int n, const int *ptr, int thr, DBuf<int> &list, int *count,
                      hipStream_t s) {
-    DBuf<int> flag;
+    DBuf<int> &flag = P->ws.i[0];
     R2P_TRY(flag.ensure(n + 1));
     k_long_flag<<<r2p_blocks(n + 1, BS), BS, 0, s>>>(n, ptr, thr, flag.p);
     R2P_LAUNCH();
@@ -479,13 +483,13 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
         k_iota<<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, A.agg.p);
         R2P_LAUNCH();
         // successive passes, each on the Galerkin product of the previous one
-        DBuf<int> crp[2], ccol[2];
-        DBuf<double> cval[2];
+        DBuf<int> *crp = P->ws.crp, *ccol = P->ws.ccol;
+        DBuf<double> *cval = P->ws.cval;
         const int *rp = A.rp.p, *col = A.col.p;
         const double *val = A.val.p;
         int cn = A.n, nc = A.n, nnzc = 0, cnnz = A.nnz;
         for (int p = 0; p < passes; p++) {
-            DBuf<int> a;
+            DBuf<int> &a = P->ws.agg;
             R2P_TRY(aggregate_pass(P, cn, rp, col, val, a, &nc, s));
             bool last = p == passes - 1;
             DBuf<int> &orp = last ? C.rp : crp[p & 1];

@@ -155,6 +155,8 @@ struct RasDyn {
     std::vector<int> h_nlev;              // levels per subdomain
     std::vector<int> h_lbase;             // first segment (level) index per subdomain
     DBuf<int> lev;                        // mtot: level of local row (natural)
+    DBuf<int> suboff;                     // ns+1: first local row of every subdomain
+    DBuf<int> indeg, queue;               // mtot: level computation (set-up only)
     DBuf<int> nlnat, nunat;               // mtot: predecessor / successor counts (natural)
     DBuf<int> pos;                        // mtot: position of local row
     DBuf<int> perm;                       // mtot: local row (natural) at position
@@ -165,9 +167,13 @@ struct RasDyn {
     DBuf<int> soff;                       // nseg+1: first slice of every level
     DBuf<int> sl_start, sl_cnt, sl_wl, sl_wu, sl_bl, sl_bu;   // per slice
     DBuf<int> sl_of;                      // mtot: slice of every position
+    DBuf<int4> meta_l, meta_u;            // per slice: (start, rows, width, entry base) of L / U
     DBuf<int> lcol, ucol;                 // entries: column position (-1 padding)
     DBuf<int> lsrc, usrc;                 // entries: block source (set-up only)
     DBuf<int> dsrc_pos;                   // mtot: diagonal block source per position
+    DBuf<int> ldiag;                      // L entries: entry of U_qp in row q (set-up only)
+    DBuf<int> xptr;                       // mtot+1: extra ILU(0) matches per position
+    DBuf<int4> xl;                        // extra matches (set-up only)
     DBuf<int> sub_lbase;                  // ns: first segment of the subdomain
     DBuf<int> sub_nlev;                   // ns
     DBuf<int> counters;                   // scratch
@@ -199,8 +205,21 @@ struct AmgLevel {
     DBuf<float> bf, xf, xof; // work vectors (fp32)
 };
 
+// Scratch of the set-up kept in the handle, so that repeated set-ups at the
+// same size allocate nothing.  Each helper names which entries it uses; no
+// two helpers that use the same entry are live at once.
+struct SetupWork {
+    DBuf<unsigned> u[6];
+    DBuf<int> i[4];
+    DBuf<double> d[1];
+    DBuf<int> agg;                        // aggregates of the current pass
+    DBuf<int> crp[2], ccol[2];            // intermediate Galerkin products
+    DBuf<double> cval[2];
+};
+
 struct r2p_cpr {
     r2p_cpr_opts o{};
+    SetupWork ws;
     r2p_jacobian *J = nullptr;
     int ready = 0;
     RasStatic rs;

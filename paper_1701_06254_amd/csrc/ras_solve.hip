@@ -28,7 +28,7 @@
 constexpr int BS = 256;
 constexpr int WG = 1024;               // threads of a subdomain workgroup
 constexpr int NWAVE = WG / 64;
-constexpr int MAXW = 4;                // blocks per row held in registers
+constexpr int MAXW = 3;                // blocks per row held in registers
 constexpr int MAXLEV = 4096;           // levels per subdomain kept in LDS
 
 // True when global row h precedes global row g in the local order.
@@ -41,26 +41,47 @@ __device__ __forceinline__ bool before(int h, int g, int n, int order, const dou
 }
 
 // ------------------------------------------------------------------ levels
-// Longest-path level, relaxed in place until nothing changes (levels only
-// grow and are bounded, so the fixed point is the longest-path depth).
-__global__ void k_levels(int mtot, int n, int order, const double *phi, const int *glob_nat,
-                         const int *aptr, const int *adj, int *lev, int *changed) {
-    int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= mtot) return;
-    int g = glob_nat[l];
-    int best = 0;
-    for (int e = aptr[l]; e < aptr[l + 1]; e++) {
-        int h = adj[e];
-        if (before(glob_nat[h], g, n, order, phi)) {
-            int v = __hip_atomic_load(&lev[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-            best = v > best ? v : best;
+// Longest-path level of every local row, one workgroup per subdomain, by
+// Kahn's algorithm in rounds: round t holds exactly the rows whose last
+// predecessor was in round t-1, so a row's round is 1 + the deepest round of
+// its predecessors (0 for rows without one).  Each row enters the
+// subdomain's queue once; the order inside a round depends on scheduling,
+// the rounds do not.
+__global__ __launch_bounds__(WG) void k_levels(const int *suboff, int n, int order,
+                                               const double *phi, const int *glob_nat,
+                                               const int *aptr, const int *adj, const int *npred,
+                                               int *indeg, int *queue, int *lev, int *nlev) {
+    __shared__ int tail;
+    int sub = blockIdx.x;
+    int a = suboff[sub], b = suboff[sub + 1];
+    if (threadIdx.x == 0) tail = a;
+    __syncthreads();
+    for (int l = a + (int)threadIdx.x; l < b; l += WG) {
+        int d = npred[l];
+        indeg[l] = d;
+        if (d == 0) queue[atomicAdd(&tail, 1)] = l;
+    }
+    __syncthreads();
+    int qs = a, qe = tail, t = 0;
+    __syncthreads();
+    while (qs < qe) {
+        for (int q = qs + (int)threadIdx.x; q < qe; q += WG) {
+            int l = queue[q];
+            lev[l] = t;
+            int g = glob_nat[l];
+            for (int e = aptr[l]; e < aptr[l + 1]; e++) {
+                int h = adj[e];
+                if (before(g, glob_nat[h], n, order, phi) && atomicSub(&indeg[h], 1) == 1)
+                    queue[atomicAdd(&tail, 1)] = h;
+            }
         }
+        __syncthreads();
+        qs = qe;
+        qe = tail;
+        t++;
+        __syncthreads();
     }
-    int cur = lev[l];
-    if (best > cur) {
-        __hip_atomic_store(&lev[l], best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        *changed = 1;
-    }
+    if (threadIdx.x == 0) nlev[sub] = t;
 }
 
 __global__ void k_pred_count(int mtot, int n, int order, const double *phi, const int *glob_nat,
@@ -71,18 +92,6 @@ __global__ void k_pred_count(int mtot, int n, int order, const double *phi, cons
     for (int e = aptr[l]; e < aptr[l + 1]; e++) a += before(glob_nat[adj[e]], g, n, order, phi);
     nl[l] = a;
     nu[l] = aptr[l + 1] - aptr[l] - a;
-}
-
-// Deepest level of every subdomain: rows of a subdomain are contiguous, so a
-// workgroup meets at most a few subdomains; it reduces in LDS first.
-__global__ void k_sub_maxlev(int mtot, int ns, const int *sub_of, const int *lev, int *mx) {
-    __shared__ int smax[64];
-    if (threadIdx.x < 64) smax[threadIdx.x] = 0;
-    __syncthreads();
-    int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < mtot) atomicMax(&smax[sub_of[l]], lev[l]);
-    __syncthreads();
-    if (threadIdx.x < ns && smax[threadIdx.x] > 0) atomicMax(&mx[threadIdx.x], smax[threadIdx.x]);
 }
 
 __global__ void k_level_count(int mtot, const int *sub_of, const int *lev, const int *lbase,
@@ -205,18 +214,94 @@ __global__ void k_fill_entries(int mtot, int n, int order, const double *phi, co
 }
 
 // ---------------------------------------------------------- factorisation
+// Block ILU(0) in IKJ form: for every predecessor q of row p, in local
+// order, L_pq = A_pq U_qq^-1, then A_pj -= L_pq U_qj for every later entry j
+// of row p that row q also holds.  The set-up splits this into
+//   1. a gather of every row's blocks into the factor arrays (all rows at
+//      once; the diagonal block goes where its inverse will be stored);
+//   2. a symbolic pass (all rows at once) that finds, for each L entry
+//      (p, q), where U_qp sits in row q, plus the rarer matches of other
+//      later entries (they need a triangle p-q-j, which the 7-point grid
+//      graph does not have; well couplings make them);
+//   3. the numeric pass, one workgroup per subdomain, level by level, which
+//      only follows the precomputed matches.
+// The updates of every target happen in the same order as in the plain
+// loop, with the same expressions, so the factors are the same.
 struct FactArgs {
     BlkSrc B;
     const int *lbase, *nlev, *soff;
     const int *sl_st, *sl_cn, *sl_bl, *sl_bu, *sl_of;
     const int *nl, *nu, *dsrc, *lcol, *ucol, *lsrc, *usrc;
+    int *ldiag;                  // per L entry: entry index of U_qp in row q
+    int *xptr;                   // mtot+1: first extra match of every position
+    int4 *xl;                    // extra matches: (e, e2, entry index in row q's U, 0)
     double *lval, *uval, *dinv;
     int *status;
 };
 
-// Block ILU(0), one workgroup per subdomain, level by level (IKJ form):
-// for every predecessor q in local order: L_pq = A_pq U_qq^-1, then
-// A_pj -= L_pq U_qj for each later entry j of row p that row q also holds.
+__device__ __forceinline__ long slice_entry(const int *sl_of, const int *sl_st, const int *sl_b,
+                                            int p, int e) {
+    int sl = sl_of[p];
+    return (long)sl_b[sl] + (p - sl_st[sl]) + (long)e * RAS_SLICE;
+}
+
+__global__ void k_bilu_gather(int mtot, FactArgs A) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= mtot) return;
+    int nlp = A.nl[p], nup = A.nu[p];
+    long bl = slice_entry(A.sl_of, A.sl_st, A.sl_bl, p, 0);
+    long bu = slice_entry(A.sl_of, A.sl_st, A.sl_bu, p, 0);
+    for (int e = 0; e < nlp; e++) {
+        long k = bl + (long)e * RAS_SLICE;
+        load_block(A.B, A.lsrc[k], &A.lval[4 * k]);
+    }
+    for (int e = 0; e < nup; e++) {
+        long k = bu + (long)e * RAS_SLICE;
+        load_block(A.B, A.usrc[k], &A.uval[4 * k]);
+    }
+    load_block(A.B, A.dsrc[p], &A.dinv[4 * (long)p]);
+}
+
+// Pass 0 counts the extra matches of every position and records the
+// diagonal match of every L entry; pass 1 writes the extra matches.
+__global__ void k_bilu_sym(int mtot, FactArgs A, int pass) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= mtot) return;
+    int nlp = A.nl[p], nup = A.nu[p];
+    long bl = slice_entry(A.sl_of, A.sl_st, A.sl_bl, p, 0);
+    long bu = slice_entry(A.sl_of, A.sl_st, A.sl_bu, p, 0);
+    int cnt = 0, out = pass ? A.xptr[p] : 0;
+    for (int e = 0; e < nlp; e++) {
+        long k = bl + (long)e * RAS_SLICE;
+        int q = A.lcol[k];
+        long buq = slice_entry(A.sl_of, A.sl_st, A.sl_bu, q, 0);
+        int nuq = A.nu[q];
+        for (int e2 = e + 1; e2 <= nlp + nup; e2++) {
+            int cj = e2 < nlp ? A.lcol[bl + (long)e2 * RAS_SLICE]
+                              : (e2 == nlp ? p : A.ucol[bu + (long)(e2 - nlp - 1) * RAS_SLICE]);
+            for (int y = 0; y < nuq; y++) {
+                long ky = buq + (long)y * RAS_SLICE;
+                if (A.ucol[ky] != cj) continue;
+                if (e2 == nlp) {
+                    if (pass == 0) A.ldiag[k] = (int)ky;
+                } else {
+                    if (pass) A.xl[out + cnt] = make_int4(e, e2, (int)ky, 0);
+                    cnt++;
+                }
+                break;
+            }
+        }
+    }
+    if (pass == 0) A.xptr[p] = cnt;
+}
+
+__device__ __forceinline__ void sub_prod(double *t, const double *l, const double *u) {
+    t[0] -= l[0] * u[0] + l[1] * u[2];
+    t[1] -= l[0] * u[1] + l[1] * u[3];
+    t[2] -= l[2] * u[0] + l[3] * u[2];
+    t[3] -= l[2] * u[1] + l[3] * u[3];
+}
+
 __global__ __launch_bounds__(WG) void k_bilu0(FactArgs A) {
     int s = blockIdx.x;
     int nlev = A.nlev[s], base = A.lbase[s];
@@ -227,54 +312,40 @@ __global__ __launch_bounds__(WG) void k_bilu0(FactArgs A) {
             if (lane >= A.sl_cn[sl]) continue;
             int p = A.sl_st[sl] + lane;
             long bl = (long)A.sl_bl[sl] + lane, bu = (long)A.sl_bu[sl] + lane;
-            int nlp = A.nl[p], nup = A.nu[p];
-            for (int e = 0; e < nlp; e++) {
-                long k = bl + (long)e * RAS_SLICE;
-                load_block(A.B, A.lsrc[k], &A.lval[4 * k]);
-            }
-            for (int e = 0; e < nup; e++) {
-                long k = bu + (long)e * RAS_SLICE;
-                load_block(A.B, A.usrc[k], &A.uval[4 * k]);
-            }
-            double d[4];
-            load_block(A.B, A.dsrc[p], d);
+            int nlp = A.nl[p];
+            int xi = A.xptr[p], xe = A.xptr[p + 1];
+            double *dp = &A.dinv[4 * (long)p];
+            double d[4] = {dp[0], dp[1], dp[2], dp[3]};
             for (int e = 0; e < nlp; e++) {
                 long k = bl + (long)e * RAS_SLICE;
                 int q = A.lcol[k];
                 double *a = &A.lval[4 * k];
                 const double *dk = &A.dinv[4 * (long)q];
-                double l0 = a[0] * dk[0] + a[1] * dk[2];
-                double l1 = a[0] * dk[1] + a[1] * dk[3];
-                double l2 = a[2] * dk[0] + a[3] * dk[2];
-                double l3 = a[2] * dk[1] + a[3] * dk[3];
-                a[0] = l0; a[1] = l1; a[2] = l2; a[3] = l3;
-                int sq = A.sl_of[q];
-                long buq = (long)A.sl_bu[sq] + (q - A.sl_st[sq]);
-                int nuq = A.nu[q];
-                // later entries of row p: remaining predecessors, the diagonal, successors
-                for (int e2 = e + 1; e2 <= nlp + nup; e2++) {
-                    int cj;
-                    double *t;
-                    if (e2 < nlp) { long k2 = bl + (long)e2 * RAS_SLICE; cj = A.lcol[k2]; t = &A.lval[4 * k2]; }
-                    else if (e2 == nlp) { cj = p; t = d; }
-                    else { long k2 = bu + (long)(e2 - nlp - 1) * RAS_SLICE; cj = A.ucol[k2]; t = &A.uval[4 * k2]; }
-                    for (int y = 0; y < nuq; y++) {
-                        long ky = buq + (long)y * RAS_SLICE;
-                        if (A.ucol[ky] == cj) {
-                            const double *u = &A.uval[4 * ky];
-                            t[0] -= l0 * u[0] + l1 * u[2];
-                            t[1] -= l0 * u[1] + l1 * u[3];
-                            t[2] -= l2 * u[0] + l3 * u[2];
-                            t[3] -= l2 * u[1] + l3 * u[3];
-                            break;
-                        }
-                    }
+                double l[4];
+                l[0] = a[0] * dk[0] + a[1] * dk[2];
+                l[1] = a[0] * dk[1] + a[1] * dk[3];
+                l[2] = a[2] * dk[0] + a[3] * dk[2];
+                l[3] = a[2] * dk[1] + a[3] * dk[3];
+                a[0] = l[0]; a[1] = l[1]; a[2] = l[2]; a[3] = l[3];
+                // later entries of row p in order: remaining L entries, the
+                // diagonal, U entries (each target is touched once per e)
+                for (; xi < xe; xi++) {
+                    int4 m = A.xl[xi];
+                    if (m.x != e || m.y > nlp) break;
+                    sub_prod(&A.lval[4 * (bl + (long)m.y * RAS_SLICE)], l, &A.uval[4 * (long)m.z]);
+                }
+                int kd = A.ldiag[k];
+                if (kd >= 0) sub_prod(d, l, &A.uval[4 * (long)kd]);
+                for (; xi < xe; xi++) {
+                    int4 m = A.xl[xi];
+                    if (m.x != e) break;
+                    sub_prod(&A.uval[4 * (bu + (long)(m.y - nlp - 1) * RAS_SLICE)], l,
+                             &A.uval[4 * (long)m.z]);
                 }
             }
             double det = d[0] * d[3] - d[1] * d[2];
             if (det == 0.0 || det != det) atomicOr(A.status, 1);
-            double *di = &A.dinv[4 * (long)p];
-            di[0] = d[3] / det; di[1] = -d[1] / det; di[2] = -d[2] / det; di[3] = d[0] / det;
+            dp[0] = d[3] / det; dp[1] = -d[1] / det; dp[2] = -d[2] / det; dp[3] = d[0] / det;
         }
         __syncthreads();
     }
@@ -320,11 +391,11 @@ __global__ void k_ras_scatter(int mtot, int n, const int *glob, const unsigned c
 template <class T>
 struct SweepArgs {
     const int *lbase, *nlev, *soff;
-    const int *sl_st, *sl_cn, *sl_bl, *sl_bu, *sl_wl, *sl_wu;
+    const int4 *mL, *mU;         // per slice: (first position, rows, width, entry base) of L / U
     const int *nl, *nu, *lcol, *ucol;
     const T *lval, *uval, *dinv, *rl;
     T *y;
-    int mtot;  // local rows over all subdomains: the extent of y
+    int mtot;                    // local rows over all subdomains: the extent of y
 };
 
 // A row's static data held in registers: for the forward sweep the gathered
@@ -342,13 +413,18 @@ struct Row {
     T d[4];
 };
 
+// Slice metadata of task `sl` (slice 0 when there is none): one uniform
+// 16-byte vector load, so that it retires in order with the other loads.
+__device__ __forceinline__ int4 load_meta(const int4 *meta, int sl) {
+    return meta[sl < 0 ? 0 : sl];
+}
+
 template <class T, bool FWD>
-__device__ __forceinline__ void fetch_row(Row<T> &R, const SweepArgs<T> &A, int sl, int lane) {
-    int sls = sl < 0 ? 0 : sl;                       // wave-uniform
-    int cnt = A.sl_cn[sls], st = A.sl_st[sls];
-    int w = FWD ? A.sl_wl[sls] : A.sl_wu[sls];
-    int b = FWD ? A.sl_bl[sls] : A.sl_bu[sls];
-    R.valid = sl >= 0 && lane < cnt;
+__device__ __forceinline__ void fetch_row(Row<T> &R, const SweepArgs<T> &A, int4 m, bool task,
+                                          int lane) {
+    int st = __builtin_amdgcn_readfirstlane(m.x), cnt = __builtin_amdgcn_readfirstlane(m.y);
+    int w = __builtin_amdgcn_readfirstlane(m.z), b = __builtin_amdgcn_readfirstlane(m.w);
+    R.valid = task && lane < cnt;
     int p = st + (lane < cnt ? lane : 0);
     R.p = p;
     R.base = b + lane;
@@ -414,10 +490,79 @@ __device__ __forceinline__ void row_update(const Row<T> &R, const T *y0, const T
     }
 }
 
-// Forward (L) then backward (U) substitution of one subdomain per workgroup
-// on the gathered right-hand side; the result overwrites y in local order.
-// In each step a wavefront issues the loads its current rows depend on,
-// then fetches its next slice, then computes and stores.
+// One triangular sweep of a subdomain: forward (L, unit diagonal) or
+// backward (U, then the inverse diagonal block).  A wavefront walks its
+// tasks (slices) level by level.  In each step it issues the loads that
+// depend on earlier levels (the y values of its current rows), then the
+// static data of its next slice, then the metadata of the slice after that,
+// computes and stores.  Loads retire in issue order, so waiting for the
+// current rows never waits for the prefetches, and a fetch never waits for
+// its own metadata: both were requested one step earlier.
+template <class T, bool FWD>
+__device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *soff, int nlev,
+                                          int wave, int lane) {
+    const int dir = FWD ? 1 : -1;
+    const int4 *meta = FWD ? A.mL : A.mU;
+    int tL = FWD ? -1 : nlev, ts = -1;
+    next_task(soff, nlev, dir, wave, tL, ts);
+    tL = __builtin_amdgcn_readfirstlane(tL);
+    ts = __builtin_amdgcn_readfirstlane(ts);
+    int nL = tL, ns = ts;
+    next_task(soff, nlev, dir, wave, nL, ns);
+    nL = __builtin_amdgcn_readfirstlane(nL);
+    ns = __builtin_amdgcn_readfirstlane(ns);
+    Row<T> cur, nxt;
+    fetch_row<T, FWD>(cur, A, load_meta(meta, ts), ts >= 0, lane);
+    int4 mn = load_meta(meta, ns);
+    for (int L = FWD ? 0 : nlev - 1; FWD ? L < nlev : L >= 0; L += dir) {
+        while (tL == L) {
+            int n2L = nL, n2s = ns;
+            next_task(soff, nlev, dir, wave, n2L, n2s);
+            n2L = __builtin_amdgcn_readfirstlane(n2L);
+            n2s = __builtin_amdgcn_readfirstlane(n2s);
+            T y0[MAXW], y1[MAXW];
+#pragma unroll
+            for (int e = 0; e < MAXW; e++) {
+                // a column outside y (never produced by the set-up) is read
+                // as the row itself rather than out of bounds
+                long q = e < cur.n ? cur.col[e] : cur.p;
+                q = (unsigned long)q < (unsigned long)A.mtot ? q : (long)cur.p;
+                y0[e] = A.y[2 * q];
+                y1[e] = A.y[2 * q + 1];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            fetch_row<T, FWD>(nxt, A, mn, ns >= 0, lane);
+            int4 mn2 = load_meta(meta, n2s);
+            // keep every load above issued before any use of the y values,
+            // so no prefetch waits behind them
+            __builtin_amdgcn_sched_barrier(0);
+            T t0, t1;
+            if (FWD) {
+                row_update(cur, y0, y1, A.lcol, A.lval, A.y, A.mtot, t0, t1);
+                if (cur.valid) {
+                    A.y[2 * (long)cur.p] = t0;
+                    A.y[2 * (long)cur.p + 1] = t1;
+                }
+            } else {
+                row_update(cur, y0, y1, A.ucol, A.uval, A.y, A.mtot, t0, t1);
+                if (cur.valid) {
+                    A.y[2 * (long)cur.p] = cur.d[0] * t0 + cur.d[1] * t1;
+                    A.y[2 * (long)cur.p + 1] = cur.d[2] * t0 + cur.d[3] * t1;
+                }
+            }
+            cur = nxt;
+            mn = mn2;
+            tL = nL;
+            ts = ns;
+            nL = n2L;
+            ns = n2s;
+        }
+        __syncthreads();
+    }
+}
+
+// Forward then backward substitution of one subdomain per workgroup on the
+// gathered right-hand side; the result overwrites y in local order.
 template <class T>
 __global__ __launch_bounds__(WG) void k_ras_sweep(SweepArgs<T> A) {
     __shared__ int soff[MAXLEV + 1];
@@ -427,54 +572,16 @@ __global__ __launch_bounds__(WG) void k_ras_sweep(SweepArgs<T> A) {
     __syncthreads();
     int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
-    for (int dir = 1; dir >= -1; dir -= 2) {
-        bool fwd = dir > 0;
-        int tL = fwd ? -1 : nlev, ts = -1;
-        next_task(soff, nlev, dir, wave, tL, ts);
-        tL = __builtin_amdgcn_readfirstlane(tL);
-        ts = __builtin_amdgcn_readfirstlane(ts);
-        Row<T> cur, nxt;
-        if (fwd) fetch_row<T, true>(cur, A, ts, lane);
-        else fetch_row<T, false>(cur, A, ts, lane);
-        for (int L = fwd ? 0 : nlev - 1; fwd ? L < nlev : L >= 0; L += dir) {
-            while (tL == L) {
-                int nL = tL, ns = ts;
-                next_task(soff, nlev, dir, wave, nL, ns);
-                nL = __builtin_amdgcn_readfirstlane(nL);
-                ns = __builtin_amdgcn_readfirstlane(ns);
-                T y0[MAXW], y1[MAXW];
-#pragma unroll
-                for (int e = 0; e < MAXW; e++) {
-                    // a column outside y (never produced by the set-up)
-                    // is read as the row itself rather than out of bounds
-                    long q = e < cur.n ? cur.col[e] : cur.p;
-                    q = (unsigned long)q < (unsigned long)A.mtot ? q : (long)cur.p;
-                    y0[e] = A.y[2 * q];
-                    y1[e] = A.y[2 * q + 1];
-                }
-                if (fwd) fetch_row<T, true>(nxt, A, ns, lane);
-                else fetch_row<T, false>(nxt, A, ns, lane);
-                T t0, t1;
-                if (fwd) {
-                    row_update(cur, y0, y1, A.lcol, A.lval, A.y, A.mtot, t0, t1);
-                    if (cur.valid) {
-                        A.y[2 * (long)cur.p] = t0;
-                        A.y[2 * (long)cur.p + 1] = t1;
-                    }
-                } else {
-                    row_update(cur, y0, y1, A.ucol, A.uval, A.y, A.mtot, t0, t1);
-                    if (cur.valid) {
-                        A.y[2 * (long)cur.p] = cur.d[0] * t0 + cur.d[1] * t1;
-                        A.y[2 * (long)cur.p + 1] = cur.d[2] * t0 + cur.d[3] * t1;
-                    }
-                }
-                cur = nxt;
-                tL = nL;
-                ts = ns;
-            }
-            __syncthreads();
-        }
-    }
+    sweep_dir<T, true>(A, soff, nlev, wave, lane);
+    sweep_dir<T, false>(A, soff, nlev, wave, lane);
+}
+
+__global__ void k_slice_meta(int nslice, const int *st, const int *cn, const int *wl,
+                             const int *bl, const int *wu, const int *bu, int4 *mL, int4 *mU) {
+    int sl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= nslice) return;
+    mL[sl] = make_int4(st[sl], cn[sl], wl[sl], bl[sl]);
+    mU[sl] = make_int4(st[sl], cn[sl], wu[sl], bu[sl]);
 }
 
 // ----------------------------------------------------------------- set-up
@@ -501,35 +608,25 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     R2P_TRY(P->pin.ensure(1 << 16));
     int nb = r2p_blocks(mtot, BS);
     // 1. levels of the dependency graph
-    R2P_HIP(hipMemsetAsync(D.lev.p, 0, sizeof(int) * mtot, s));
-    int *changed = D.counters.p;
-    int *hflag = (int *)P->pin.p;
-    for (int it = 0; it < mtot + 2; it += 8) {
-        R2P_HIP(hipMemsetAsync(changed, 0, sizeof(int), s));
-        for (int k = 0; k < 8; k++) {
-            k_levels<<<nb, BS, 0, s>>>(mtot, ph.n, order, J->phi_o.p, S.glob_nat.p, S.aptr.p,
-                                       S.adj.p, D.lev.p, changed);
-            R2P_LAUNCH();
-        }
-        R2P_HIP(hipMemcpyAsync(hflag, changed, sizeof(int), hipMemcpyDeviceToHost, s));
-        R2P_HIP(hipStreamSynchronize(s));
-        if (*hflag == 0) break;
-    }
     k_pred_count<<<nb, BS, 0, s>>>(mtot, ph.n, order, J->phi_o.p, S.glob_nat.p, S.aptr.p, S.adj.p,
                                    D.nlnat.p, D.nunat.p);
     R2P_LAUNCH();
-    // 2. level segments
-    int *dmax = D.counters.p + 64;
-    R2P_HIP(hipMemsetAsync(dmax, 0, sizeof(int) * ns, s));
-    k_sub_maxlev<<<nb, BS, 0, s>>>(mtot, ns, S.sub_of.p, D.lev.p, dmax);
+    R2P_TRY(D.suboff.ensure(ns + 1));
+    R2P_TRY(D.indeg.ensure(mtot));
+    R2P_TRY(D.queue.ensure(mtot));
+    R2P_HIP(hipMemcpyAsync(D.suboff.p, S.h_off.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice, s));
+    int *dnlev = D.counters.p + 64;
+    int *hflag = (int *)P->pin.p;
+    k_levels<<<ns, WG, 0, s>>>(D.suboff.p, ph.n, order, J->phi_o.p, S.glob_nat.p, S.aptr.p,
+                               S.adj.p, D.nlnat.p, D.indeg.p, D.queue.p, D.lev.p, dnlev);
     R2P_LAUNCH();
-    R2P_HIP(hipMemcpyAsync(hflag, dmax, sizeof(int) * ns, hipMemcpyDeviceToHost, s));
+    // 2. level segments
+    R2P_HIP(hipMemcpyAsync(hflag, dnlev, sizeof(int) * ns, hipMemcpyDeviceToHost, s));
     R2P_HIP(hipStreamSynchronize(s));
     D.h_nlev.assign(ns, 0);
     D.h_lbase.assign(ns + 1, 0);
     for (int t = 0; t < ns; t++) {
-        int cnt = S.h_off[t + 1] - S.h_off[t];
-        D.h_nlev[t] = cnt > 0 ? hflag[t] + 1 : 0;
+        D.h_nlev[t] = hflag[t];
         if (D.h_nlev[t] > MAXLEV) {
             r2p_set_error("subdomain %d has %d dependency levels (limit %d)", t, D.h_nlev[t], MAXLEV);
             return R2P_EINVAL;
@@ -550,8 +647,8 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     R2P_TRY(r2p_scan_int(D.lptr_dev.p, D.lptr_dev.p, nseg + 1, nullptr, P->iscratch, P->pin, s));
     // 3. positions: stable sort by (level segment, descending predecessor count)
     {
-        DBuf<unsigned> key, val, kt, vt;
-        DBuf<int> hist;
+        DBuf<unsigned> &key = P->ws.u[0], &val = P->ws.u[1], &kt = P->ws.u[2], &vt = P->ws.u[3];
+        DBuf<int> &hist = P->ws.i[0];
         R2P_TRY(key.ensure(mtot));
         R2P_TRY(val.ensure(mtot));
         R2P_TRY(kt.ensure(mtot));
@@ -588,6 +685,12 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     int nle = 0, nue = 0;
     R2P_TRY(r2p_scan_int(D.sl_bl.p, D.sl_bl.p, nslice + 1, &nle, P->iscratch, P->pin, s));
     R2P_TRY(r2p_scan_int(D.sl_bu.p, D.sl_bu.p, nslice + 1, &nue, P->iscratch, P->pin, s));
+    R2P_TRY(D.meta_l.ensure(nslice));
+    R2P_TRY(D.meta_u.ensure(nslice));
+    k_slice_meta<<<r2p_blocks(nslice, BS), BS, 0, s>>>(nslice, D.sl_start.p, D.sl_cnt.p, D.sl_wl.p,
+                                                       D.sl_bl.p, D.sl_wu.p, D.sl_bu.p,
+                                                       D.meta_l.p, D.meta_u.p);
+    R2P_LAUNCH();
     D.nlent = nle;
     D.nuent = nue;
     // RAS_SLICE entries of padding after each array: an empty last slice is
@@ -620,6 +723,21 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     F.sl_of = D.sl_of.p; F.nl = D.nl.p; F.nu = D.nu.p; F.dsrc = D.dsrc_pos.p;
     F.lcol = D.lcol.p; F.ucol = D.ucol.p; F.lsrc = D.lsrc.p; F.usrc = D.usrc.p;
     F.lval = D.f64.lval.p; F.uval = D.f64.uval.p; F.dinv = D.f64.dinv.p; F.status = P->status.p;
+    R2P_TRY(D.ldiag.ensure(nle + RAS_SLICE));
+    R2P_TRY(D.xptr.ensure(mtot + 1));
+    R2P_HIP(hipMemsetAsync(D.ldiag.p, 0xff, sizeof(int) * (size_t)(nle + RAS_SLICE), s));
+    R2P_HIP(hipMemsetAsync(D.xptr.p + mtot, 0, sizeof(int), s));
+    F.ldiag = D.ldiag.p; F.xptr = D.xptr.p; F.xl = nullptr;
+    k_bilu_gather<<<nb, BS, 0, s>>>(mtot, F);
+    R2P_LAUNCH();
+    k_bilu_sym<<<nb, BS, 0, s>>>(mtot, F, 0);
+    R2P_LAUNCH();
+    int nx = 0;
+    R2P_TRY(r2p_scan_int(D.xptr.p, D.xptr.p, mtot + 1, &nx, P->iscratch, P->pin, s));
+    R2P_TRY(D.xl.ensure(nx));
+    F.xl = D.xl.p;
+    k_bilu_sym<<<nb, BS, 0, s>>>(mtot, F, 1);
+    R2P_LAUNCH();
     k_bilu0<<<ns, WG, 0, s>>>(F);
     R2P_LAUNCH();
     if (P->o.precision == R2P_FP32) {
@@ -659,8 +777,7 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     R2P_LAUNCH();
     SweepArgs<T> A;
     A.lbase = D.sub_lbase.p; A.nlev = D.sub_nlev.p; A.soff = D.soff.p;
-    A.sl_st = D.sl_start.p; A.sl_cn = D.sl_cnt.p; A.sl_bl = D.sl_bl.p; A.sl_bu = D.sl_bu.p;
-    A.sl_wl = D.sl_wl.p; A.sl_wu = D.sl_wu.p;
+    A.mL = D.meta_l.p; A.mU = D.meta_u.p;
     A.nl = D.nl.p; A.nu = D.nu.p; A.lcol = D.lcol.p; A.ucol = D.ucol.p;
     A.lval = F.lval.p; A.uval = F.uval.p; A.dinv = F.dinv.p; A.rl = rl; A.y = y;
     A.mtot = mtot;

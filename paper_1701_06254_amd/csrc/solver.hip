@@ -24,14 +24,16 @@ int r2p_decouple_jacobian(r2p_jacobian *J, int kind, hipStream_t s);
 int r2p_newton_update(r2p_model *m, const double *y, double *x, double ds_max, hipStream_t s);
 
 constexpr int BS = 256;
-constexpr int EPT = 8;                  // elements per thread in the dot kernels
+constexpr int EPT = 16;                 // elements of w per thread in the multi-dot
 constexpr int TILE = BS * EPT;
 constexpr int MAXV = 65;                // basis vectors + 1 (w.w)
 
 // ----------------------------------------------------------- multi-dot
-// h[k] = V_k . w (k < nv) and h[nv] = w . w.  Per-workgroup partial sums,
-// then the last workgroup to finish (ticket) adds the partials in block
-// order, so the result does not depend on scheduling.
+// h[k] = V_k . w (k < nv) and h[nv] = w . w.  Each thread keeps EPT
+// elements of w in registers and streams the basis vectors past them; each
+// workgroup writes one partial per k.  The last workgroup to finish (ticket)
+// adds the partials: L lanes per k, each over a fixed stride of workgroups,
+// then a fixed butterfly, so the result does not depend on scheduling.
 __global__ __launch_bounds__(BS) void k_mdot(const double *V, long ld, int nv, const double *w,
                                              long N, double *part, double *h, unsigned *ticket) {
     __shared__ double red[BS / 64][MAXV];
@@ -48,11 +50,14 @@ __global__ __launch_bounds__(BS) void k_mdot(const double *V, long ld, int nv, c
         double acc = 0.0;
         if (k < nv) {
             const double *vk = V + (long)k * ld;
+            double t[EPT];
 #pragma unroll
             for (int e = 0; e < EPT; e++) {
                 long i = base + (long)e * BS;
-                acc += (i < N ? vk[i] : 0.0) * wv[e];
+                t[e] = i < N ? vk[i] : 0.0;
             }
+#pragma unroll
+            for (int e = 0; e < EPT; e++) acc += t[e] * wv[e];
         } else {
 #pragma unroll
             for (int e = 0; e < EPT; e++) acc += wv[e] * wv[e];
@@ -72,20 +77,19 @@ __global__ __launch_bounds__(BS) void k_mdot(const double *V, long ld, int nv, c
     __syncthreads();
     if (!last) return;
     __threadfence();
-    __shared__ double sred[BS];
     int nb = gridDim.x;
-    for (int k = 0; k <= nv; k++) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += BS)
-            s += __hip_atomic_load(&part[(long)b * MAXV + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sred[threadIdx.x] = s;
-        __syncthreads();
-        for (int st = BS / 2; st > 0; st >>= 1) {
-            if (threadIdx.x < st) sred[threadIdx.x] += sred[threadIdx.x + st];
-            __syncthreads();
+    int L = 64;                                   // lanes per k: a power of two
+    while (L > 1 && L * (nv + 1) > BS) L >>= 1;
+    int kpp = BS / L;                             // k values per pass
+    for (int k0 = 0; k0 <= nv; k0 += kpp) {
+        int k = k0 + (int)threadIdx.x / L, j = threadIdx.x & (L - 1);
+        double sum = 0.0;
+        if (k <= nv) {
+#pragma unroll 8
+            for (int b = j; b < nb; b += L) sum += part[(long)b * MAXV + k];
         }
-        if (threadIdx.x == 0) h[k] = sred[0];
-        __syncthreads();
+        for (int d = L >> 1; d > 0; d >>= 1) sum += __shfl_xor(sum, d, 64);
+        if (j == 0 && k <= nv) h[k] = sum;
     }
     if (threadIdx.x == 0) *ticket = 0u;
 }
