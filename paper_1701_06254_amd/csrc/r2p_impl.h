@@ -123,13 +123,19 @@ __host__ __device__ inline int slot_offset(int s, int nx, int nxy) {
 // Block ILU(0) factors of every overlapped subdomain.  Rows ("positions" p,
 // concatenated over subdomains) are stored in level order of each
 // subdomain's dependency graph, rows of a level sorted by descending number
-// of predecessors.  Every level is cut into slices of 64 consecutive
-// positions (one wavefront, one row per lane); a slice stores its L blocks
-// (predecessors, ascending local order) and its U blocks (successors) in
-// sliced-ELL form: entry e of lane t of slice k sits at base[k] + 64 e + t,
-// so each load instruction of a wavefront is contiguous.  Padding entries
-// (e >= the row's count) are never read.
+// of predecessors.  Every level is cut into slices of RAS_ROWS consecutive
+// positions, one wavefront per slice and two lanes per row (lane 2r + h
+// holds the entries e = h, h + 2, ... of row r).  A slice stores its L
+// blocks (predecessors, ascending local order) and its U blocks (successors)
+// in sliced-ELL form with RAS_SLICE entries per column: entry e of row r
+// sits at base + (e / 2) RAS_SLICE + 2r + (e mod 2), so each load
+// instruction of a wavefront is contiguous.  Padding entries (e >= the
+// row's count) hold column -1 and zero blocks.
 constexpr int RAS_SLICE = 64;
+constexpr int RAS_ROWS = 32;
+__host__ __device__ inline long ras_entry(long base, int r, int e) {
+    return base + (long)(e >> 1) * RAS_SLICE + 2 * r + (e & 1);
+}
 template <class T>
 struct RasFactors {
     DBuf<T> lval, uval;   // 4 per entry (row-major 2x2)

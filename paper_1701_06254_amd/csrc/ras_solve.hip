@@ -10,13 +10,14 @@
 // sequence as a sequential ILU(0) in that order and the factors match it.
 //
 // One workgroup (16 wavefronts) processes one subdomain level by level, a
-// workgroup barrier between levels; a wavefront takes a 64-row slice, one
-// row per lane.  Levels are a latency chain, so every wavefront fetches the
-// static data of its next slice (factor blocks, columns, right-hand side)
-// into registers right after issuing the current slice's dependent loads:
-// loads retire in issue order, so waiting for the current rows never waits
-// for the prefetch, and the prefetch overlaps the compute, the store and the
-// barrier.  The gather of the right-hand side into local order and the
+// workgroup barrier between levels; a wavefront takes a slice of 32 rows,
+// two lanes per row (each lane takes every other block of the row, so the
+// six couplings of a grid cell stay in registers).  Levels are a latency
+// chain, so every wavefront fetches the static data of its next slice
+// (factor blocks, columns, right-hand side) into registers right after
+// issuing the current slice's dependent loads: loads retire in issue order,
+// so waiting for the current rows never waits for the prefetch, and the
+// prefetch overlaps the compute, the store and the barrier.  The gather of the right-hand side into local order and the
 // restricted scatter of the result run as separate full-device kernels.
 //
 // Compiled without floating-point contraction (reproducible block products).
@@ -28,7 +29,8 @@
 constexpr int BS = 256;
 constexpr int WG = 1024;               // threads of a subdomain workgroup
 constexpr int NWAVE = WG / 64;
-constexpr int MAXW = 3;                // blocks per row held in registers
+constexpr int NCW = NWAVE;             // sweep: wavefronts sharing the slices of a level
+constexpr int MAXK = 3;                // entries per lane held in registers (two lanes per row)
 constexpr int MAXLEV = 4096;           // levels per subdomain kept in LDS
 
 // True when global row h precedes global row g in the local order.
@@ -132,7 +134,7 @@ __global__ void k_perm_gather(int mtot, const unsigned *perm, const int *glob_na
 
 __global__ void k_slice_count(int nseg, const int *lptr, int *nsl) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < nseg) nsl[g] = (lptr[g + 1] - lptr[g] + RAS_SLICE - 1) / RAS_SLICE;
+    if (g < nseg) nsl[g] = (lptr[g + 1] - lptr[g] + RAS_ROWS - 1) / RAS_ROWS;
     if (g == nseg) nsl[g] = 0;
 }
 
@@ -144,8 +146,8 @@ __global__ void k_slice_fill(int nseg, const int *lptr, const int *soff, int nsl
     if (g >= nseg) return;
     int a = soff[g], b = soff[g + 1];
     for (int sl = a + (int)threadIdx.x; sl < b; sl += blockDim.x) {
-        int start = lptr[g] + (sl - a) * RAS_SLICE;
-        int cnt = min(RAS_SLICE, lptr[g + 1] - start);
+        int start = lptr[g] + (sl - a) * RAS_ROWS;
+        int cnt = min(RAS_ROWS, lptr[g + 1] - start);
         int ml = 0, mu = 0;
         for (int t = 0; t < cnt; t++) {
             ml = max(ml, nl[start + t]);
@@ -161,7 +163,7 @@ __global__ void k_slice_fill(int nseg, const int *lptr, const int *soff, int nsl
 
 __global__ void k_slice_size(int nslice, const int *w, int *sz) {
     int sl = blockIdx.x * blockDim.x + threadIdx.x;
-    if (sl < nslice) sz[sl] = w[sl] * RAS_SLICE;
+    if (sl < nslice) sz[sl] = (w[sl] + 1) / 2 * RAS_SLICE;
     if (sl == nslice) sz[sl] = 0;
 }
 
@@ -175,22 +177,20 @@ __global__ void k_fill_entries(int mtot, int n, int order, const double *phi, co
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= mtot) return;
     int l = permi[p], g = glob_nat[l];
-    int sl = sl_of[p], lane = p - sl_st[sl];
-    long bl = (long)sl_bl[sl] + lane, bu = (long)sl_bu[sl] + lane;
+    int sl = sl_of[p], r = p - sl_st[sl];
+    long bl = sl_bl[sl], bu = sl_bu[sl];
     int el = 0, eu = 0;
     for (int t = aptr[l]; t < aptr[l + 1]; t++) {
         int h = adj[t];
         int gh = glob_nat[h];
         if (before(gh, g, n, order, phi)) {
-            long k = bl + (long)el * RAS_SLICE;
+            long k = ras_entry(bl, r, el++);
             lcol[k] = pos[h];
             lsrc[k] = asrc[t];
-            el++;
         } else {
-            long k = bu + (long)eu * RAS_SLICE;
+            long k = ras_entry(bu, r, eu++);
             ucol[k] = pos[h];
             usrc[k] = asrc[t];
-            eu++;
         }
     }
     for (int part = 0; part < 2; part++) {
@@ -199,16 +199,17 @@ __global__ void k_fill_entries(int mtot, int n, int order, const double *phi, co
         int *col = part == 0 ? lcol : ucol;
         int *src = part == 0 ? lsrc : usrc;
         for (int u = 1; u < cnt; u++) {
-            int vc = col[b + (long)u * RAS_SLICE], vs = src[b + (long)u * RAS_SLICE];
+            long ku = ras_entry(b, r, u);
+            int vc = col[ku], vs = src[ku];
             int vg = glob[vc];
             int k = u - 1;
-            while (k >= 0 && before(vg, glob[col[b + (long)k * RAS_SLICE]], n, order, phi)) {
-                col[b + (long)(k + 1) * RAS_SLICE] = col[b + (long)k * RAS_SLICE];
-                src[b + (long)(k + 1) * RAS_SLICE] = src[b + (long)k * RAS_SLICE];
+            while (k >= 0 && before(vg, glob[col[ras_entry(b, r, k)]], n, order, phi)) {
+                col[ras_entry(b, r, k + 1)] = col[ras_entry(b, r, k)];
+                src[ras_entry(b, r, k + 1)] = src[ras_entry(b, r, k)];
                 k--;
             }
-            col[b + (long)(k + 1) * RAS_SLICE] = vc;
-            src[b + (long)(k + 1) * RAS_SLICE] = vs;
+            col[ras_entry(b, r, k + 1)] = vc;
+            src[ras_entry(b, r, k + 1)] = vs;
         }
     }
 }
@@ -239,10 +240,16 @@ struct FactArgs {
     int *status;
 };
 
+// Entry e of position p in the L (sl_b = sl_bl) or U (sl_bu) arrays.
 __device__ __forceinline__ long slice_entry(const int *sl_of, const int *sl_st, const int *sl_b,
                                             int p, int e) {
     int sl = sl_of[p];
-    return (long)sl_b[sl] + (p - sl_st[sl]) + (long)e * RAS_SLICE;
+    return ras_entry(sl_b[sl], p - sl_st[sl], e);
+}
+
+// Entry e of a row whose entry 0 sits at rb (rb = ras_entry(base, r, 0)).
+__device__ __forceinline__ long ent(long rb, int e) {
+    return rb + (long)(e >> 1) * RAS_SLICE + (e & 1);
 }
 
 __global__ void k_bilu_gather(int mtot, FactArgs A) {
@@ -252,11 +259,11 @@ __global__ void k_bilu_gather(int mtot, FactArgs A) {
     long bl = slice_entry(A.sl_of, A.sl_st, A.sl_bl, p, 0);
     long bu = slice_entry(A.sl_of, A.sl_st, A.sl_bu, p, 0);
     for (int e = 0; e < nlp; e++) {
-        long k = bl + (long)e * RAS_SLICE;
+        long k = ent(bl, e);
         load_block(A.B, A.lsrc[k], &A.lval[4 * k]);
     }
     for (int e = 0; e < nup; e++) {
-        long k = bu + (long)e * RAS_SLICE;
+        long k = ent(bu, e);
         load_block(A.B, A.usrc[k], &A.uval[4 * k]);
     }
     load_block(A.B, A.dsrc[p], &A.dinv[4 * (long)p]);
@@ -272,15 +279,15 @@ __global__ void k_bilu_sym(int mtot, FactArgs A, int pass) {
     long bu = slice_entry(A.sl_of, A.sl_st, A.sl_bu, p, 0);
     int cnt = 0, out = pass ? A.xptr[p] : 0;
     for (int e = 0; e < nlp; e++) {
-        long k = bl + (long)e * RAS_SLICE;
+        long k = ent(bl, e);
         int q = A.lcol[k];
         long buq = slice_entry(A.sl_of, A.sl_st, A.sl_bu, q, 0);
         int nuq = A.nu[q];
         for (int e2 = e + 1; e2 <= nlp + nup; e2++) {
-            int cj = e2 < nlp ? A.lcol[bl + (long)e2 * RAS_SLICE]
-                              : (e2 == nlp ? p : A.ucol[bu + (long)(e2 - nlp - 1) * RAS_SLICE]);
+            int cj = e2 < nlp ? A.lcol[ent(bl, e2)]
+                              : (e2 == nlp ? p : A.ucol[ent(bu, e2 - nlp - 1)]);
             for (int y = 0; y < nuq; y++) {
-                long ky = buq + (long)y * RAS_SLICE;
+                long ky = ent(buq, y);
                 if (A.ucol[ky] != cj) continue;
                 if (e2 == nlp) {
                     if (pass == 0) A.ldiag[k] = (int)ky;
@@ -311,13 +318,13 @@ __global__ __launch_bounds__(WG) void k_bilu0(FactArgs A) {
         for (int sl = s0 + wave; sl < s1; sl += NWAVE) {
             if (lane >= A.sl_cn[sl]) continue;
             int p = A.sl_st[sl] + lane;
-            long bl = (long)A.sl_bl[sl] + lane, bu = (long)A.sl_bu[sl] + lane;
+            long bl = ras_entry(A.sl_bl[sl], lane, 0), bu = ras_entry(A.sl_bu[sl], lane, 0);
             int nlp = A.nl[p];
             int xi = A.xptr[p], xe = A.xptr[p + 1];
             double *dp = &A.dinv[4 * (long)p];
             double d[4] = {dp[0], dp[1], dp[2], dp[3]};
             for (int e = 0; e < nlp; e++) {
-                long k = bl + (long)e * RAS_SLICE;
+                long k = ent(bl, e);
                 int q = A.lcol[k];
                 double *a = &A.lval[4 * k];
                 const double *dk = &A.dinv[4 * (long)q];
@@ -332,14 +339,14 @@ __global__ __launch_bounds__(WG) void k_bilu0(FactArgs A) {
                 for (; xi < xe; xi++) {
                     int4 m = A.xl[xi];
                     if (m.x != e || m.y > nlp) break;
-                    sub_prod(&A.lval[4 * (bl + (long)m.y * RAS_SLICE)], l, &A.uval[4 * (long)m.z]);
+                    sub_prod(&A.lval[4 * ent(bl, m.y)], l, &A.uval[4 * (long)m.z]);
                 }
                 int kd = A.ldiag[k];
                 if (kd >= 0) sub_prod(d, l, &A.uval[4 * (long)kd]);
                 for (; xi < xe; xi++) {
                     int4 m = A.xl[xi];
                     if (m.x != e) break;
-                    sub_prod(&A.uval[4 * (bu + (long)(m.y - nlp - 1) * RAS_SLICE)], l,
+                    sub_prod(&A.uval[4 * ent(bu, m.y - nlp - 1)], l,
                              &A.uval[4 * (long)m.z]);
                 }
             }
@@ -398,18 +405,21 @@ struct SweepArgs {
     int mtot;                    // local rows over all subdomains: the extent of y
 };
 
-// A row's static data held in registers: for the forward sweep the gathered
-// right-hand side and the first MAXW L blocks, for the backward sweep the
-// forward result, the first MAXW U blocks and the inverse diagonal.  Loads
-// are unconditional (slots past a row's count or a slice's width read the
-// zero padding or this row itself) so the fetch has no data-dependent branch.
+// A row's static data held in the registers of its two lanes: lane h of
+// the pair holds the row's entries e = h, h + 2, ... up to MAXK of them
+// (the first 2 MAXK blocks of the row between the pair), and both lanes
+// hold the row's right-hand side (forward: the gathered residual; backward:
+// the forward result) and, backward, its inverse diagonal block.  Loads are
+// unconditional (columns past a slice's width re-read its last column, or
+// the zero padding after the arrays for an empty slice) so the fetch has no
+// data-dependent branch.
 template <class T>
 struct Row {
-    int p, n, base;
+    int p, n, base, h;
     bool valid;
     T a0, a1;
-    int col[MAXW];
-    T v[MAXW][4];
+    int col[MAXK];
+    T v[MAXK][4];
     T d[4];
 };
 
@@ -423,9 +433,11 @@ template <class T, bool FWD>
 __device__ __forceinline__ void fetch_row(Row<T> &R, const SweepArgs<T> &A, int4 m, bool task,
                                           int lane) {
     int st = __builtin_amdgcn_readfirstlane(m.x), cnt = __builtin_amdgcn_readfirstlane(m.y);
-    int w = __builtin_amdgcn_readfirstlane(m.z), b = __builtin_amdgcn_readfirstlane(m.w);
-    R.valid = task && lane < cnt;
-    int p = st + (lane < cnt ? lane : 0);
+    int wc = __builtin_amdgcn_readfirstlane(m.z), b = __builtin_amdgcn_readfirstlane(m.w);
+    int r = lane >> 1;
+    R.h = lane & 1;
+    R.valid = task && r < cnt;
+    int p = st + (r < cnt ? r : 0);
     R.p = p;
     R.base = b + lane;
     // lanes past the slice's rows see only padding columns (-1): they take
@@ -437,16 +449,12 @@ __device__ __forceinline__ void fetch_row(Row<T> &R, const SweepArgs<T> &A, int4
     const int *cols = FWD ? A.lcol : A.ucol;
     const T *vals = FWD ? A.lval : A.uval;
 #pragma unroll
-    for (int e = 0; e < MAXW; e++) {
-        // Loads are unconditional so that the wait counts stay exact; columns
-        // past the slice width re-read its last column (or, for an empty
-        // slice, the padding that follows the entry arrays) and are masked
-        // by the row length later.
-        int ee = e < w ? e : (w > 0 ? w - 1 : 0);
-        long k = (long)R.base + (long)ee * RAS_SLICE;
-        R.col[e] = cols[k];
-        R.v[e][0] = vals[4 * k]; R.v[e][1] = vals[4 * k + 1];
-        R.v[e][2] = vals[4 * k + 2]; R.v[e][3] = vals[4 * k + 3];
+    for (int k = 0; k < MAXK; k++) {
+        int kk = k < wc ? k : (wc > 0 ? wc - 1 : 0);
+        long idx = (long)R.base + (long)kk * RAS_SLICE;
+        R.col[k] = cols[idx];
+        R.v[k][0] = vals[4 * idx]; R.v[k][1] = vals[4 * idx + 1];
+        R.v[k][2] = vals[4 * idx + 2]; R.v[k][3] = vals[4 * idx + 3];
     }
     if (!FWD) {
         const T *di = &A.dinv[4 * (long)p];
@@ -454,50 +462,111 @@ __device__ __forceinline__ void fetch_row(Row<T> &R, const SweepArgs<T> &A, int4
     }
 }
 
-// Next slice this wavefront works on after slice `sl` of level `L` (sweeping
+// Next slice compute wavefront `wave` works on after slice `sl` of level `L` (sweeping
 // up when dir > 0, down otherwise), or level -1 / nlev when there is none.
 __device__ __forceinline__ void next_task(const int *soff, int nlev, int dir, int wave, int &L,
                                           int &sl) {
-    if (sl >= 0 && sl + NWAVE < soff[L + 1]) { sl += NWAVE; return; }
+    if (sl >= 0 && sl + NCW < soff[L + 1]) { sl += NCW; return; }
     for (L += dir; L >= 0 && L < nlev; L += dir)
         if (soff[L] + wave < soff[L + 1]) { sl = soff[L] + wave; return; }
     sl = -1;
 }
 
-// One row of a sweep: t = a - sum_e B_e y_{col_e} over the row's blocks in
-// order, the first MAXW from registers, any further ones loaded here.
+// One row of a sweep, t = a - sum_e B_e y_{col_e}.  Each lane of the pair
+// subtracts its own entries (the even lane from a, the odd lane from 0),
+// the first MAXK from registers and any further ones loaded here; the two
+// partial results are then added, so both lanes hold the same t.
 template <class T>
 __device__ __forceinline__ void row_update(const Row<T> &R, const T *y0, const T *y1,
                                            const int *cols, const T *vals, const T *y, int mtot,
                                            T &t0, T &t1) {
-    t0 = R.a0;
-    t1 = R.a1;
+    t0 = R.h == 0 ? R.a0 : (T)0;
+    t1 = R.h == 0 ? R.a1 : (T)0;
 #pragma unroll
-    for (int e = 0; e < MAXW; e++) {
-        T d0 = R.v[e][0] * y0[e] + R.v[e][1] * y1[e];
-        T d1 = R.v[e][2] * y0[e] + R.v[e][3] * y1[e];
-        bool on = e < R.n;
+    for (int k = 0; k < MAXK; k++) {
+        T d0 = R.v[k][0] * y0[k] + R.v[k][1] * y1[k];
+        T d1 = R.v[k][2] * y0[k] + R.v[k][3] * y1[k];
+        bool on = R.h + 2 * k < R.n;
         t0 -= on ? d0 : (T)0;
         t1 -= on ? d1 : (T)0;
     }
-    for (int e = MAXW; e < R.n; e++) {
-        long k = (long)R.base + (long)e * RAS_SLICE;
-        long q = cols[k];
+    for (int k = MAXK; R.h + 2 * k < R.n; k++) {
+        long idx = (long)R.base + (long)k * RAS_SLICE;
+        long q = cols[idx];
         q = (unsigned long)q < (unsigned long)mtot ? q : (long)R.p;
         T a0 = y[2 * q], a1 = y[2 * q + 1];
-        t0 -= vals[4 * k] * a0 + vals[4 * k + 1] * a1;
-        t1 -= vals[4 * k + 2] * a0 + vals[4 * k + 3] * a1;
+        t0 -= vals[4 * idx] * a0 + vals[4 * idx + 1] * a1;
+        t1 -= vals[4 * idx + 2] * a0 + vals[4 * idx + 3] * a1;
     }
+    t0 += __shfl_xor(t0, 1, 64);
+    t1 += __shfl_xor(t1, 1, 64);
+}
+
+// One step of a triangular sweep: the wavefront's current slice `cur`
+// (task tL, ts), whose static data are in registers.  It first passes the
+// workgroup barriers of every level before tL that it has not passed yet,
+// then issues the loads that depend on earlier levels (the y values of its
+// rows), then the static data of its next slice into `nxt` and the
+// metadata of the slice after that, computes and stores.  Loads retire in
+// issue order, so waiting for the current rows never waits for the
+// prefetches, and a fetch never waits for its own metadata: both were
+// requested one step earlier.  The caller alternates the two row buffers,
+// so no register copy forces a prefetch to land within its own step.
+template <class T, bool FWD>
+__device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *soff, int nlev,
+                                           int wave, int lane, Row<T> &cur, Row<T> &nxt,
+                                           int4 &mn, int &tL, int &ts, int &nL, int &ns,
+                                           int &passed) {
+    const int dir = FWD ? 1 : -1;
+    const int4 *meta = FWD ? A.mL : A.mU;
+    int rank = FWD ? tL : nlev - 1 - tL;          // levels this one waits for
+    while (passed < rank) {
+        __syncthreads();
+        passed++;
+    }
+    int n2L = nL, n2s = ns;
+    next_task(soff, nlev, dir, wave, n2L, n2s);
+    n2L = __builtin_amdgcn_readfirstlane(n2L);
+    n2s = __builtin_amdgcn_readfirstlane(n2s);
+    T y0[MAXK], y1[MAXK];
+#pragma unroll
+    for (int k = 0; k < MAXK; k++) {
+        // a column outside y (never produced by the set-up) is read as the
+        // row itself rather than out of bounds
+        long q = cur.h + 2 * k < cur.n ? cur.col[k] : cur.p;
+        q = (unsigned long)q < (unsigned long)A.mtot ? q : (long)cur.p;
+        y0[k] = A.y[2 * q];
+        y1[k] = A.y[2 * q + 1];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_row<T, FWD>(nxt, A, mn, ns >= 0, lane);
+    mn = load_meta(meta, n2s);
+    // keep every load above issued before any use of the y values
+    __builtin_amdgcn_sched_barrier(0);
+    T t0, t1;
+    if (FWD) {
+        row_update(cur, y0, y1, A.lcol, A.lval, A.y, A.mtot, t0, t1);
+        if (cur.valid && cur.h == 0) {
+            A.y[2 * (long)cur.p] = t0;
+            A.y[2 * (long)cur.p + 1] = t1;
+        }
+    } else {
+        row_update(cur, y0, y1, A.ucol, A.uval, A.y, A.mtot, t0, t1);
+        if (cur.valid && cur.h == 0) {
+            A.y[2 * (long)cur.p] = cur.d[0] * t0 + cur.d[1] * t1;
+            A.y[2 * (long)cur.p + 1] = cur.d[2] * t0 + cur.d[3] * t1;
+        }
+    }
+    tL = nL;
+    ts = ns;
+    nL = n2L;
+    ns = n2s;
 }
 
 // One triangular sweep of a subdomain: forward (L, unit diagonal) or
 // backward (U, then the inverse diagonal block).  A wavefront walks its
-// tasks (slices) level by level.  In each step it issues the loads that
-// depend on earlier levels (the y values of its current rows), then the
-// static data of its next slice, then the metadata of the slice after that,
-// computes and stores.  Loads retire in issue order, so waiting for the
-// current rows never waits for the prefetches, and a fetch never waits for
-// its own metadata: both were requested one step earlier.
+// tasks (slices) in level order; every wavefront passes one workgroup
+// barrier per level, in the same sequence, wherever it has work.
 template <class T, bool FWD>
 __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *soff, int nlev,
                                           int wave, int lane) {
@@ -511,53 +580,18 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *soff
     next_task(soff, nlev, dir, wave, nL, ns);
     nL = __builtin_amdgcn_readfirstlane(nL);
     ns = __builtin_amdgcn_readfirstlane(ns);
-    Row<T> cur, nxt;
-    fetch_row<T, FWD>(cur, A, load_meta(meta, ts), ts >= 0, lane);
+    Row<T> ra, rb;
+    fetch_row<T, FWD>(ra, A, load_meta(meta, ts), ts >= 0, lane);
     int4 mn = load_meta(meta, ns);
-    for (int L = FWD ? 0 : nlev - 1; FWD ? L < nlev : L >= 0; L += dir) {
-        while (tL == L) {
-            int n2L = nL, n2s = ns;
-            next_task(soff, nlev, dir, wave, n2L, n2s);
-            n2L = __builtin_amdgcn_readfirstlane(n2L);
-            n2s = __builtin_amdgcn_readfirstlane(n2s);
-            T y0[MAXW], y1[MAXW];
-#pragma unroll
-            for (int e = 0; e < MAXW; e++) {
-                // a column outside y (never produced by the set-up) is read
-                // as the row itself rather than out of bounds
-                long q = e < cur.n ? cur.col[e] : cur.p;
-                q = (unsigned long)q < (unsigned long)A.mtot ? q : (long)cur.p;
-                y0[e] = A.y[2 * q];
-                y1[e] = A.y[2 * q + 1];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            fetch_row<T, FWD>(nxt, A, mn, ns >= 0, lane);
-            int4 mn2 = load_meta(meta, n2s);
-            // keep every load above issued before any use of the y values,
-            // so no prefetch waits behind them
-            __builtin_amdgcn_sched_barrier(0);
-            T t0, t1;
-            if (FWD) {
-                row_update(cur, y0, y1, A.lcol, A.lval, A.y, A.mtot, t0, t1);
-                if (cur.valid) {
-                    A.y[2 * (long)cur.p] = t0;
-                    A.y[2 * (long)cur.p + 1] = t1;
-                }
-            } else {
-                row_update(cur, y0, y1, A.ucol, A.uval, A.y, A.mtot, t0, t1);
-                if (cur.valid) {
-                    A.y[2 * (long)cur.p] = cur.d[0] * t0 + cur.d[1] * t1;
-                    A.y[2 * (long)cur.p + 1] = cur.d[2] * t0 + cur.d[3] * t1;
-                }
-            }
-            cur = nxt;
-            mn = mn2;
-            tL = nL;
-            ts = ns;
-            nL = n2L;
-            ns = n2s;
-        }
+    int passed = 0;
+    while (ts >= 0) {
+        sweep_step<T, FWD>(A, soff, nlev, wave, lane, ra, rb, mn, tL, ts, nL, ns, passed);
+        if (ts < 0) break;
+        sweep_step<T, FWD>(A, soff, nlev, wave, lane, rb, ra, mn, tL, ts, nL, ns, passed);
+    }
+    while (passed < nlev) {
         __syncthreads();
+        passed++;
     }
 }
 
@@ -580,8 +614,8 @@ __global__ void k_slice_meta(int nslice, const int *st, const int *cn, const int
                              const int *bl, const int *wu, const int *bu, int4 *mL, int4 *mU) {
     int sl = blockIdx.x * blockDim.x + threadIdx.x;
     if (sl >= nslice) return;
-    mL[sl] = make_int4(st[sl], cn[sl], wl[sl], bl[sl]);
-    mU[sl] = make_int4(st[sl], cn[sl], wu[sl], bu[sl]);
+    mL[sl] = make_int4(st[sl], cn[sl], (wl[sl] + 1) / 2, bl[sl]);
+    mU[sl] = make_int4(st[sl], cn[sl], (wu[sl] + 1) / 2, bu[sl]);
 }
 
 // ----------------------------------------------------------------- set-up
@@ -856,14 +890,14 @@ extern "C" int r2p_ras_export(r2p_cpr *P, int sub, int *glob, int *level, unsign
         if (level) level[i] = lv[pm[p]];
         if (owned) owned[i] = ow[p];
         if (dinv) memcpy(dinv + 4L * i, dv.data() + 4L * p, 4 * sizeof(double));
-        int sl = slof[p], lane = p - slst[sl];
+        int sl = slof[p], r = p - slst[sl];
         for (int part = 0; part < 2; part++) {
             int cnt = part == 0 ? nl[p] : nu[p];
-            long base = (part == 0 ? slbl[sl] : slbu[sl]) + lane;
+            long base = part == 0 ? slbl[sl] : slbu[sl];
             const std::vector<int> &cc = part == 0 ? lc : uc;
             const std::vector<double> &vv = part == 0 ? lvv : uvv;
             for (int e = 0; e < cnt; e++, k++) {
-                long idx = base + (long)e * RAS_SLICE;
+                long idx = ras_entry(base, r, e);
                 if (erow) erow[k] = g[p];
                 if (ecol) ecol[k] = g[cc[idx]];
                 if (eval) memcpy(eval + 4 * k, vv.data() + 4 * idx, 4 * sizeof(double));
