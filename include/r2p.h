@@ -31,6 +31,8 @@
 #ifndef R2P_H
 #define R2P_H
 
+#include <stdint.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -121,7 +123,12 @@ typedef struct {
     double ds_max;     /* largest saturation change per Newton iteration (0.2; <= 0 disables) */
     r2p_cpr_opts cpr;
     r2p_solve_opts lin;
+    int guess_rule;    /* when x_guess is taken: R2P_GUESS_SCALED_INF (its scaled residual
+                          max-norm is below that of x^n), R2P_GUESS_L2 (its residual
+                          2-norm is), R2P_GUESS_TRY (always; if Newton does not converge
+                          from it, the step starts again from x^n) */
 } r2p_newton_opts;
+enum { R2P_GUESS_SCALED_INF = 0, R2P_GUESS_L2 = 1, R2P_GUESS_TRY = 2 };
 
 #define R2P_HIST 32
 typedef struct {
@@ -240,7 +247,9 @@ int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y,
  * to [0,1]).  Standard Newton solves every system to lin.rtol; with
  * R2P_FORCING_EW the tolerance follows the second forcing term of Eq 26,
  * clipped to [0.01, 0.1].  x_guess (device, may be NULL): a first iterate
- * to try; it is used only if its scaled residual is below that of x^n.
+ * to try, taken according to opts->guess_rule (by default only if its
+ * scaled residual max-norm is below that of x^n); info->newton_its and
+ * linear_its count every attempt, res_hist the last one.
  * x: device, in x^n, out x^{n+1}.  Synchronous.  Returns 0, or
  * R2P_NOT_CONVERGED with x unchanged (the caller shortens dt). */
 int r2p_newton_step(r2p_model *m, double *x, double dt, const double *x_guess,
@@ -250,6 +259,71 @@ int r2p_newton_step(r2p_model *m, double *x, double dt, const double *x_guess,
  * 1, theta 0.25, coarse 500, 20 levels, 4 rounds, 2 passes, FP64; FGMRES(30) to 1e-8
  * with 300 iterations; Newton 20 iterations to 1e-8, ds_max 0.2. */
 void r2p_default_newton_opts(r2p_newton_opts *o);
+
+/* -------------------------------------------------- learned warm start
+ * A 3D convolutional network that predicts the increment (dp / 100 psi,
+ * ds_w / 0.1) of a time step from the state at its start; its prediction is the
+ * first Newton iterate x_guess of r2p_newton_step, taken only when it lowers
+ * the residual (the paper's Algorithm 1 with a different starting point).
+ * Layers: conv 6 -> 32 + ReLU, `blocks` residual blocks
+ * h <- h + conv(relu(conv(h))), conv 32 -> 2; 3x3x3 taps, zero padding.
+ * Tensors are channels-last [crop][z][y][x][32] bfloat16 (uint16_t bit
+ * patterns, round to nearest even) unless stated; feature and output
+ * channels beyond 6 / 2 are zero.  Products accumulate in FP32; the master
+ * weights are FP32, trained by Adam (beta 0.9 / 0.999, eps 1e-8) on the
+ * mean squared error.  The compact parameter vector holds, per layer in the
+ * order in, a_0, b_0, ..., a_{K-1}, b_{K-1}, out, W[27][cout][cin] then
+ * b[cout]; tap t = 9 (dz+1) + 3 (dy+1) + (dx+1).  Every entry point is
+ * asynchronous on `stream` unless stated. */
+typedef struct r2p_cnn r2p_cnn;
+int r2p_cnn_param_count(int blocks, long *n_host);
+/* Weights start at zero: set them with r2p_cnn_set_params.  Synchronous. */
+int r2p_cnn_create(int blocks, r2p_cnn **out);
+int r2p_cnn_destroy(r2p_cnn *cnn);
+/* Host FP32 compact vectors (r2p_cnn_param_count entries).  Synchronous;
+ * setting parameters also resets the Adam state. */
+int r2p_cnn_set_params(r2p_cnn *cnn, const float *theta_host);
+int r2p_cnn_get_params(r2p_cnn *cnn, float *theta_host);
+int r2p_cnn_get_grads(r2p_cnn *cnn, float *grad_host);
+/* feat: device bf16 [nb][nz][ny][nx][32]; out: device FP32 [nb*nz*ny*nx][2]. */
+int r2p_cnn_forward(r2p_cnn *cnn, const uint16_t *feat, int nb, int nz, int ny, int nx,
+                    float *out, void *stream);
+/* Forward, mean squared error against target (device FP32 [V][2]) and the
+ * gradient of every parameter (kept in the handle); loss_host (may be NULL)
+ * receives the loss, which makes the call synchronous. */
+int r2p_cnn_backward(r2p_cnn *cnn, const uint16_t *feat, const float *target, int nb, int nz,
+                     int ny, int nx, double *loss_host, void *stream);
+/* One Adam step with learning rate lr on the gradients of the last backward. */
+int r2p_cnn_sgd_step(r2p_cnn *cnn, float lr, void *stream);
+/* One 32 -> 32 layer on caller tensors (device): out = epilogue(bias +
+ * sum_t sum_i x[v + s off_t][i] w[t][o][i]) with s = -1 when flip (the
+ * input-gradient form, w then holding the per-tap transposed weights);
+ * epilogue: + addend, kept where mask > 0, ReLU when relu.  bias, addend,
+ * mask may be NULL; out (bf16) and/or outf (FP32 [V][32]).  x, w, out 16-byte
+ * aligned. */
+int r2p_cnn_conv(const uint16_t *x, int nb, int nz, int ny, int nx, const uint16_t *w,
+                 const float *bias, const uint16_t *addend, const uint16_t *mask, int relu,
+                 int flip, uint16_t *out, float *outf, void *stream);
+/* Weight and bias gradients of one 32 -> 32 layer: dw[t][o][i] =
+ * sum_v gy[v][o] x[v + off_t][i], db[o] = sum_v gy[v][o] (device FP32).
+ * Synchronous. */
+int r2p_cnn_conv_dw(const uint16_t *gy, const uint16_t *x, int nb, int nz, int ny, int nx,
+                    float *dw, float *db, void *stream);
+/* Network input of a state x (device, the layout of r2p_initial_state) at the
+ * start of a step of length dt: per cell (p - 4800)/1000, s_w,
+ * (ln kx - 4.6)/2, (phi - 0.2)/0.1, a signed well source log(1 + V) with V
+ * the pore-volume fraction a perforation's well can move in dt (+ injector,
+ * - producer), ln dt; feat: device bf16 [n][32]. */
+int r2p_cnn_features(r2p_model *m, const double *x, double dt, uint16_t *feat, void *stream);
+/* Training target of a step: ((p_new - p_old)/100, (s_new - s_old)/0.1) per
+ * cell, device FP32 [n][2]. */
+int r2p_cnn_targets(r2p_model *m, const double *x_old, const double *x_new, float *target,
+                    void *stream);
+/* x_guess = x + prediction (p += 100 out_0, s_w += 0.1 out_1 clipped to
+ * [0,1]; a rate well's p_b moves by its perforations' mean dp, a BHP well's
+ * stays). */
+int r2p_cnn_warm_start(r2p_model *m, r2p_cnn *cnn, const double *x, double dt, double *x_guess,
+                       void *stream);
 
 const char *r2p_last_error(void);
 

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libr2p.so")
-SOURCES = ["common.hip", "physics.hip", "ras.hip", "ras_solve.hip", "amg.hip", "solver.hip"]
+SOURCES = ["common.hip", "physics.hip", "ras.hip", "ras_solve.hip", "amg.hip", "solver.hip", "cnn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

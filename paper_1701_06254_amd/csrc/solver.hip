@@ -402,6 +402,7 @@ extern "C" void r2p_default_newton_opts(r2p_newton_opts *o) {
     o->lin.restart = 30;
     o->lin.maxit = 300;
     o->lin.rtol = 1e-8;
+    o->guess_rule = R2P_GUESS_SCALED_INF;
 }
 
 struct NewtonWork {
@@ -419,52 +420,14 @@ static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-extern "C" int r2p_newton_step(r2p_model *m, double *x, double dt, const double *x_guess,
-                               const r2p_newton_opts *o, r2p_newton_info *info, void *stream) {
-    double T0 = now_ms();
-    if (!m || !x || !o) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
-    if (!(dt > 0) || o->max_newton < 1 || o->max_newton >= R2P_HIST || !(o->tol > 0)) {
-        r2p_set_error("invalid Newton options");
-        return R2P_EINVAL;
-    }
-    R2P_TRY(check_opts(&o->cpr));
-    hipStream_t s = (hipStream_t)stream;
-    static thread_local NewtonWork *W = nullptr;
-    if (!W || W->m != m) {
-        delete W;
-        W = new NewtonWork();
-        W->m = m;
-        R2P_TRY(r2p_jacobian_create(m, &W->J));
-        R2P_TRY(r2p_cpr_create(&W->P));
-    }
-    long N = 2L * (m->ph.n + m->ph.nw);
-    R2P_TRY(W->xold.ensure(N));
-    R2P_TRY(W->xk.ensure(N));
-    R2P_TRY(W->b.ensure(N));
-    R2P_TRY(W->y.ensure(N));
-    R2P_TRY(W->t.ensure(N));
-    r2p_newton_info inf{};
-    R2P_HIP(hipMemcpyAsync(W->xold.p, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-    R2P_HIP(hipMemcpyAsync(W->xk.p, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-    Krylov &K = krylov_for(W->P);
-    R2P_TRY(K.h.ensure(MAXV));
-    R2P_TRY(K.pin.ensure(sizeof(double) * MAXV * 2));
-    if (!K.ticket.p) {
-        R2P_TRY(K.ticket.ensure(1));
-        R2P_HIP(hipMemsetAsync(K.ticket.p, 0, sizeof(unsigned), s));
-    }
-    if (x_guess) {
-        double ng = 0.0, n0 = 0.0;
-        R2P_TRY(r2p_assemble_jacobian(m, x_guess, W->xold.p, dt, W->J, W->b.p, stream));
-        int rc = r2p_residual_norm(m, W->b.p, dt, &ng, stream);
-        R2P_TRY(r2p_assemble_jacobian(m, x, W->xold.p, dt, W->J, W->b.p, stream));
-        R2P_TRY(r2p_residual_norm(m, W->b.p, dt, &n0, stream));
-        if (rc == 0 && ng < n0) {
-            R2P_HIP(hipMemcpyAsync(W->xk.p, x_guess, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-            inf.used_guess = 1;
-        }
-    }
-    int status = R2P_NOT_CONVERGED;
+// Newton iterations of Algorithm 1 from the iterate in W->xk (old state in
+// W->xold); status 0 when the scaled residual test passes.  Iteration counts
+// and timings accumulate in inf.
+static int newton_loop(NewtonWork *W, Krylov &K, r2p_model *m, double dt,
+                       const r2p_newton_opts *o, long N, hipStream_t s, r2p_newton_info &inf,
+                       int &status) {
+    void *stream = (void *)s;
+    status = R2P_NOT_CONVERGED;
     double eta = 0.1, prev_fn = 0.0, prev_rn = 0.0;
     for (int it = 0; it <= o->max_newton; it++) {
         double ta = now_ms();
@@ -508,7 +471,80 @@ extern "C" int r2p_newton_step(r2p_model *m, double *x, double dt, const double 
             prev_fn = fn;
         }
         R2P_TRY(r2p_newton_update(m, W->y.p, W->xk.p, o->ds_max, s));
-        inf.newton_its = it + 1;
+        inf.newton_its++;
+    }
+    return 0;
+}
+
+extern "C" int r2p_newton_step(r2p_model *m, double *x, double dt, const double *x_guess,
+                               const r2p_newton_opts *o, r2p_newton_info *info, void *stream) {
+    double T0 = now_ms();
+    if (!m || !x || !o) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
+    if (!(dt > 0) || o->max_newton < 1 || o->max_newton >= R2P_HIST || !(o->tol > 0) ||
+        o->guess_rule < 0 || o->guess_rule > 2) {
+        r2p_set_error("invalid Newton options");
+        return R2P_EINVAL;
+    }
+    R2P_TRY(check_opts(&o->cpr));
+    hipStream_t s = (hipStream_t)stream;
+    static thread_local NewtonWork *W = nullptr;
+    if (!W || W->m != m) {
+        delete W;
+        W = new NewtonWork();
+        W->m = m;
+        R2P_TRY(r2p_jacobian_create(m, &W->J));
+        R2P_TRY(r2p_cpr_create(&W->P));
+    }
+    long N = 2L * (m->ph.n + m->ph.nw);
+    R2P_TRY(W->xold.ensure(N));
+    R2P_TRY(W->xk.ensure(N));
+    R2P_TRY(W->b.ensure(N));
+    R2P_TRY(W->y.ensure(N));
+    R2P_TRY(W->t.ensure(N));
+    r2p_newton_info inf{};
+    R2P_HIP(hipMemcpyAsync(W->xold.p, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    R2P_HIP(hipMemcpyAsync(W->xk.p, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    Krylov &K = krylov_for(W->P);
+    R2P_TRY(K.h.ensure(MAXV));
+    R2P_TRY(K.pin.ensure(sizeof(double) * MAXV * 2));
+    if (!K.ticket.p) {
+        R2P_TRY(K.ticket.ensure(1));
+        R2P_HIP(hipMemsetAsync(K.ticket.p, 0, sizeof(unsigned), s));
+    }
+    if (x_guess) {
+        double ng = 0.0, n0 = 0.0, hb[2];
+        int rc = 0;
+        bool take = o->guess_rule == R2P_GUESS_TRY;
+        if (!take) {
+            R2P_TRY(r2p_assemble_jacobian(m, x_guess, W->xold.p, dt, W->J, W->b.p, stream));
+            if (o->guess_rule == R2P_GUESS_L2) {
+                R2P_TRY(mdot(K, nullptr, 0, W->b.p, N, s, hb));
+                ng = hb[0];
+                rc = ng == ng ? 0 : R2P_ENAN;
+            } else {
+                rc = r2p_residual_norm(m, W->b.p, dt, &ng, stream);
+            }
+            R2P_TRY(r2p_assemble_jacobian(m, x, W->xold.p, dt, W->J, W->b.p, stream));
+            if (o->guess_rule == R2P_GUESS_L2) {
+                R2P_TRY(mdot(K, nullptr, 0, W->b.p, N, s, hb));
+                n0 = hb[0];
+            } else {
+                R2P_TRY(r2p_residual_norm(m, W->b.p, dt, &n0, stream));
+            }
+            take = rc == 0 && ng < n0;
+        }
+        if (take) {
+            R2P_HIP(hipMemcpyAsync(W->xk.p, x_guess, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+            inf.used_guess = 1;
+        }
+    }
+    int status = R2P_NOT_CONVERGED;
+    R2P_TRY(newton_loop(W, K, m, dt, o, N, s, inf, status));
+    if (status != 0 && inf.used_guess) {
+        // the learned start did not converge: start again from x^n
+        R2P_HIP(hipMemcpyAsync(W->xk.p, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        inf.used_guess = 0;
+        R2P_TRY(newton_loop(W, K, m, dt, o, N, s, inf, status));
     }
     if (status == 0)
         R2P_HIP(hipMemcpyAsync(x, W->xk.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));

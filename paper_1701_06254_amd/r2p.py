@@ -59,7 +59,8 @@ class SolveInfo(C.Structure):
 
 class NewtonOpts(C.Structure):
     _fields_ = [("max_newton", C.c_int), ("tol", C.c_double), ("forcing", C.c_int),
-                ("ds_max", C.c_double), ("cpr", CprOpts), ("lin", SolveOpts)]
+                ("ds_max", C.c_double), ("cpr", CprOpts), ("lin", SolveOpts),
+                ("guess_rule", C.c_int)]
 
 
 class NewtonInfo(C.Structure):
@@ -80,8 +81,13 @@ def solve_opts(restart=30, maxit=300, rtol=1e-8):
     return SolveOpts(restart, maxit, rtol)
 
 
-def newton_opts(max_newton=20, tol=1e-8, forcing=FORCING_FIXED, ds_max=0.2, cpr=None, lin=None):
-    return NewtonOpts(max_newton, tol, forcing, ds_max, cpr or cpr_opts(), lin or solve_opts())
+GUESS_SCALED_INF, GUESS_L2, GUESS_TRY = 0, 1, 2
+
+
+def newton_opts(max_newton=20, tol=1e-8, forcing=FORCING_FIXED, ds_max=0.2, cpr=None, lin=None,
+                guess_rule=GUESS_SCALED_INF):
+    return NewtonOpts(max_newton, tol, forcing, ds_max, cpr or cpr_opts(), lin or solve_opts(),
+                      guess_rule)
 
 
 EXPORTS = ["r2p_model_create", "r2p_model_destroy", "r2p_model_sizes", "r2p_initial_state",
@@ -90,7 +96,10 @@ EXPORTS = ["r2p_model_create", "r2p_model_destroy", "r2p_model_sizes", "r2p_init
            "r2p_cpr_destroy", "r2p_setup_cpr", "r2p_cpr_apply", "r2p_amg_vcycle",
            "r2p_ras_apply", "r2p_amg_info", "r2p_amg_export_level", "r2p_ras_info",
            "r2p_ras_export", "r2p_solve", "r2p_newton_step", "r2p_default_newton_opts",
-           "r2p_last_error"]
+           "r2p_cnn_param_count", "r2p_cnn_create", "r2p_cnn_destroy", "r2p_cnn_set_params",
+           "r2p_cnn_get_params", "r2p_cnn_get_grads", "r2p_cnn_forward", "r2p_cnn_backward",
+           "r2p_cnn_sgd_step", "r2p_cnn_conv", "r2p_cnn_conv_dw", "r2p_cnn_features",
+           "r2p_cnn_targets", "r2p_cnn_warm_start", "r2p_last_error"]
 
 
 def load(path=LIB_PATH):
@@ -127,6 +136,21 @@ def load(path=LIB_PATH):
         "r2p_newton_step": [vp, vp, C.c_double, vp, C.POINTER(NewtonOpts),
                             C.POINTER(NewtonInfo), vp],
         "r2p_default_newton_opts": [C.POINTER(NewtonOpts)],
+        "r2p_cnn_param_count": [C.c_int, C.POINTER(C.c_long)],
+        "r2p_cnn_create": [C.c_int, C.POINTER(vp)],
+        "r2p_cnn_destroy": [vp],
+        "r2p_cnn_set_params": [vp, vp],
+        "r2p_cnn_get_params": [vp, vp],
+        "r2p_cnn_get_grads": [vp, vp],
+        "r2p_cnn_forward": [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp],
+        "r2p_cnn_backward": [vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, dp, vp],
+        "r2p_cnn_sgd_step": [vp, C.c_float, vp],
+        "r2p_cnn_conv": [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, C.c_int,
+                         C.c_int, vp, vp, vp],
+        "r2p_cnn_conv_dw": [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp],
+        "r2p_cnn_features": [vp, vp, C.c_double, vp, vp],
+        "r2p_cnn_targets": [vp, vp, vp, vp, vp],
+        "r2p_cnn_warm_start": [vp, vp, vp, C.c_double, vp, vp],
         "r2p_last_error": [],
     }
     for name, args in sig.items():
@@ -366,3 +390,92 @@ def default_newton_opts():
     o = NewtonOpts()
     load().r2p_default_newton_opts(C.byref(o))
     return o
+
+
+class Cnn:
+    """The warm-start network (r2p_cnn): bf16 activations, FP32 master weights."""
+
+    def __init__(self, blocks=4):
+        L = load()
+        n = C.c_long()
+        _check(L.r2p_cnn_param_count(blocks, C.byref(n)))
+        self.nparams = n.value
+        self.blocks = blocks
+        h = C.c_void_p()
+        _check(L.r2p_cnn_create(blocks, C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                load().r2p_cnn_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        a = _np(theta, np.float32)
+        assert a.size == self.nparams
+        _check(load().r2p_cnn_set_params(self.h, a.ctypes.data_as(C.c_void_p)))
+
+    def get_params(self):
+        a = np.zeros(self.nparams, np.float32)
+        _check(load().r2p_cnn_get_params(self.h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def get_grads(self):
+        a = np.zeros(self.nparams, np.float32)
+        _check(load().r2p_cnn_get_grads(self.h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def forward(self, feat, shape, out=None):
+        """feat: int16 device tensor of bf16 bits [V*32]; shape (nb, nz, ny, nx)."""
+        import torch
+        nb, nz, ny, nx = shape
+        V = nb * nz * ny * nx
+        out = torch.empty(2 * V, dtype=torch.float32, device="cuda") if out is None else out
+        _check(load().r2p_cnn_forward(self.h, _ptr(feat), nb, nz, ny, nx, _ptr(out), _stream()))
+        return out
+
+    def backward(self, feat, target, shape):
+        nb, nz, ny, nx = shape
+        loss = C.c_double()
+        _check(load().r2p_cnn_backward(self.h, _ptr(feat), _ptr(target), nb, nz, ny, nx,
+                                       C.byref(loss), _stream()))
+        return loss.value
+
+    def step(self, lr):
+        _check(load().r2p_cnn_sgd_step(self.h, float(lr), _stream()))
+
+    def warm_start(self, model, x, dt, x_guess=None):
+        x_guess = model.tensor() if x_guess is None else x_guess
+        _check(load().r2p_cnn_warm_start(model.h, self.h, _ptr(x), float(dt), _ptr(x_guess),
+                                         _stream()))
+        return x_guess
+
+
+def cnn_conv(x, shape, w, bias=None, addend=None, mask=None, relu=False, flip=False,
+             out=None, outf=None):
+    nb, nz, ny, nx = shape
+    _check(load().r2p_cnn_conv(_ptr(x), nb, nz, ny, nx, _ptr(w), _ptr(bias), _ptr(addend),
+                               _ptr(mask), int(relu), int(flip), _ptr(out), _ptr(outf), _stream()))
+
+
+def cnn_conv_dw(gy, x, shape, dw, db):
+    nb, nz, ny, nx = shape
+    _check(load().r2p_cnn_conv_dw(_ptr(gy), _ptr(x), nb, nz, ny, nx, _ptr(dw), _ptr(db),
+                                  _stream()))
+
+
+def cnn_features(model, x, dt, feat=None):
+    import torch
+    feat = torch.empty(model.n * 32, dtype=torch.int16, device="cuda") if feat is None else feat
+    _check(load().r2p_cnn_features(model.h, _ptr(x), float(dt), _ptr(feat), _stream()))
+    return feat
+
+
+def cnn_targets(model, x_old, x_new, target=None):
+    import torch
+    target = torch.empty(2 * model.n, dtype=torch.float32, device="cuda") if target is None else target
+    _check(load().r2p_cnn_targets(model.h, _ptr(x_old), _ptr(x_new), _ptr(target), _stream()))
+    return target
