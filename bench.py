@@ -18,6 +18,9 @@ Prints one JSON line on stdout (progress goes to stderr):
   ms_per_step      mean wall time of one time step (plain FP64);
   fp32             the same steps with the FP32 preconditioner (FP64 FGMRES),
                    with the field difference against the FP64 run;
+  fp32_learned     the same steps with the FP32 preconditioner and the learned
+                   warm start (network trained beforehand, untimed, on seeded
+                   smaller models of the same family; training time stated);
   roofline         the RAS apply (gather + level-scheduled triangular sweeps +
                    restricted scatter, the largest single kernel of a solve):
                    algorithmic bytes per apply over its HIP-event-timed mean
@@ -180,6 +183,84 @@ def cpu_baseline(w, gpu_its_per_solve, dt, sample_its):
                        f"scaled to the {gpu_its_per_solve:.1f} iterations of the mean GPU solve")
 
 
+def learned_run(args, model, x0, x64, dts, form, log):
+    """FP32 preconditioner plus the learned warm start on the same steps.
+
+    The network is trained first (not timed) on increments of seeded
+    80x80x50 models of the same family (correlated field, wells 40 cells
+    apart, 4,000 STB/d injectors, 4,000 psi producers), each run from its cold
+    start by the same step-length controller as the timed run (0.1, 0.1,
+    0.2, 0.4, 0.8 days).  Timed steps then take
+    the network's iterate first and fall back to x^n when Newton does not
+    converge from it."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1701_06254_amd import r2p, warmstart
+    o64 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form))
+    t0 = time.perf_counter()
+    pairs = []
+    for seed in range(1001, 1001 + args.train_models):
+        w = workloads.make_gaussian(nx=80, ny=80, nz=50, seed=seed, well_pattern=2)
+        m = r2p.Model(w)
+        xs = m.initial_state()
+        warmstart.collect_pairs(m, xs, [0.1, 0.1, 0.2, 0.4, 0.8], o64, pairs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net = r2p.Cnn(blocks=4)
+    net.set_params(warmstart.init_params(np.random.default_rng(7)))
+    losses = warmstart.train(net, pairs, (50, 80, 80), args.train_iters, batch=2, lr=1e-3,
+                             seed=3, log=log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"learned start: {len(pairs)} pairs in {t1 - t0:.1f} s, {args.train_iters} Adam steps "
+        f"in {t2 - t1:.1f} s, loss {np.mean(losses[:20]):.3e} -> {np.mean(losses[-20:]):.3e}")
+    # inference throughput on the full grid (algorithmic flops of the
+    # unpadded layers: 6->32, 8 x 32->32, 32->2, 3x3x3 taps)
+    feat = r2p.cnn_features(model, x0, dts[0])
+    g = model.w["grid"]
+    shape = (1, g["nz"], g["ny"], g["nx"])
+    t_fwd = time_on_stream(lambda: net.forward(feat, shape), 5)
+    flop = 2 * 27 * (6 * 32 + 8 * 32 * 32 + 32 * 2) * model.n
+    o = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, precision=r2p.FP32),
+                        guess_rule=r2p.GUESS_TRY)
+    xl = x0.clone()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    recs = []
+    for k, dt in enumerate(dts):
+        guess = net.warm_start(model, xl, dt)
+        info = model.newton_step(xl, dt, o, x_guess=guess)
+        recs.append(dict(dt=dt, status=info.status, newton=info.newton_its,
+                         linear=info.linear_its, ms_setup=info.ms_setup,
+                         ms_solve=info.ms_solve, ms_assemble=info.ms_assemble,
+                         ms_total=info.ms_total, used=info.used_guess))
+        log(f"fp32+learned step {k}: dt {dt:.4g} d status {info.status} newton {info.newton_its} "
+            f"linear {info.linear_its} guess {info.used_guess} total {info.ms_total:.0f} ms")
+        if info.status != 0:
+            break
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t3) * 1e3 / max(len(recs), 1)
+    sm = summarise(recs)
+    n = model.n
+    p64, s64 = x64[0:2 * n:2], x64[1:2 * n:2]
+    pl, sl = xl[0:2 * n:2], xl[1:2 * n:2]
+    return dict(ms_per_step=round(ms, 3), solve_ms=round(sm["solve_ms"], 3),
+                newton_its=sm["solves"], linear_its_per_solve=round(sm["its_per_solve"], 2),
+                guess_taken=int(sum(r["used"] for r in recs)), steps=len(recs),
+                cnn_forward_ms=round(t_fwd, 3),
+                cnn_tflops=round(flop / (t_fwd * 1e-3) / 1e12, 1),
+                converged=all(r["status"] == 0 for r in recs),
+                rel_err_p=float(torch.linalg.norm(pl - p64) / torch.linalg.norm(p64)),
+                rel_err_sw=float(torch.linalg.norm(sl - s64) /
+                                 max(float(torch.linalg.norm(s64)), 1e-300)),
+                training={"models": args.train_models, "pairs": len(pairs),
+                          "adam_steps": args.train_iters, "data_s": round(t1 - t0, 2),
+                          "train_s": round(t2 - t1, 2),
+                          "loss_first20": float(np.mean(losses[:20])),
+                          "loss_last20": float(np.mean(losses[-20:]))})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +271,10 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=20)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-models", type=int, default=16,
+                    help="seeded 80x80x50 models of the same family that give training pairs")
+    ap.add_argument("--train-iters", type=int, default=1500)
     ap.add_argument("--kernels-only", action="store_true",
                     help="for hardware-counter runs: set up the first Newton system of the "
                          "workload, then run 5 RAS applies, 5 V-cycles, 5 SpMVs and 5 copies "
@@ -264,6 +349,10 @@ def main():
                                      max(float(torch.linalg.norm(s_64)), 1e-300)),
                     learned_warm_start=None)
 
+    learned = None
+    if not args.no_learned and not args.no_fp32:
+        learned = learned_run(args, model, x0, x, accepted, form, log)
+
     # per-kernel timing on the last state's first Newton system
     J = r2p.Jacobian(model)
     J.assemble(x, x, dt_next)
@@ -306,6 +395,7 @@ def main():
                      "frac": round(ras_gbs / HBM_PEAK_GBS, 4), "traffic": ras_traffic(),
                      "bytes_per_launch": rb, "local_rows": m_tot, "offdiag_blocks": nblk},
         "fp32": fp32,
+        "fp32_learned": learned,
     }
     if not args.no_cpu_baseline:
         try:

@@ -12,6 +12,22 @@ import numpy as np
 from . import r2p
 
 
+def init_params(rng, blocks=4, channels=32, out_scale=0.1):
+    """Initial compact parameter vector (layer order of r2p_cnn_set_params):
+    He-normal weights (fan-in 27 cin), zero biases; the second convolution of
+    every block and the output layer scaled by out_scale so that training
+    starts near identity blocks and a small output."""
+    parts = []
+    dims = [(6, channels)] + [(channels, channels)] * (2 * blocks) + [(channels, 2)]
+    for l, (cin, cout) in enumerate(dims):
+        std = np.sqrt(2.0 / (27 * cin))
+        if l == len(dims) - 1 or (l > 0 and l % 2 == 0):
+            std *= out_scale
+        parts.append(rng.normal(0.0, std, 27 * cout * cin))
+        parts.append(np.zeros(cout))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def collect_pairs(model, x, dts, opts, pairs=None):
     """Run one implicit step per entry of dts from state x (in place) and
     append (features, target, dt) device tensors of every accepted step."""
