@@ -256,3 +256,69 @@ def test_newton_steps_match_oracle(dev, orc):
     xh = _h(xg)
     for sl in (slice(0, 2 * n, 2), slice(1, 2 * n, 2)):
         assert np.linalg.norm(xh[sl] - xo[sl]) <= 1e-6 * np.linalg.norm(xo[sl])
+
+
+# ------------------------------------------------ mixed precision (FP32)
+def test_fp32_preconditioner_apply_close_to_oracle(dev, orc):
+    """CPR with factors, hierarchy and vectors in FP32 (the coarsest inverse,
+    residuals and FGMRES in FP64): one application against the FP64 oracle.
+    The bound is FP32 storage error propagated through the two stages."""
+    w = workloads.make_small()
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
+        dev, orc, w, 2, orc.cpr_opts(), dev.cpr_opts(precision=dev.FP32))
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal(mo.N)
+    f[2 * mo.n + 1::2] = 0.0
+    zg = _h(P.apply(_t(f)))
+    zo = Po.apply(f)
+    err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
+    print(f"FP32 preconditioner: relative difference of one CPR application {err:.2e}")
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("variant", ["fp32", "ew", "abf"])
+def test_newton_variants_match_oracle(dev, orc, variant):
+    """The same 10 steps with the FP32 preconditioner, with Eisenstat-Walker
+    forcing (Eq 26, second choice) and with ABF decoupling: the Newton test
+    fixes the fields, so each must stay within 1e-6 of the FP64 oracle run
+    with the same options (FP32: the standard FP64 oracle)."""
+    w = workloads.make_small()
+    n = w["grid"]["n"]
+    mo = orc.Model(w)
+    xo = mo.initial_state()
+    mg = dev.Model(w)
+    xg = mg.initial_state()
+    if variant == "fp32":
+        go = dev.newton_opts(cpr=dev.cpr_opts(precision=dev.FP32))
+        oo, forcing = orc.cpr_opts(), 0
+    elif variant == "ew":
+        go = dev.newton_opts(forcing=dev.FORCING_EW)
+        oo, forcing = orc.cpr_opts(), 1
+    else:
+        go = dev.newton_opts(cpr=dev.cpr_opts(decouple=dev.DEC_ABF))
+        oo, forcing = orc.cpr_opts(decouple=orc.DEC_ABF), 0
+    lin_g = lin_o = 0
+    for step in range(w["steps"]):
+        rc, ni, li, _ = mo.newton_step(xo, w["dt"], oo, forcing=forcing)
+        assert rc == 0
+        info = mg.newton_step(xg, w["dt"], go)
+        assert info.status == 0
+        lin_g += info.linear_its
+        lin_o += li
+    xh = _h(xg)
+    for sl in (slice(0, 2 * n, 2), slice(1, 2 * n, 2)):
+        assert np.linalg.norm(xh[sl] - xo[sl]) <= 1e-6 * np.linalg.norm(xo[sl])
+    print(f"{variant}: linear iterations GPU {lin_g}, oracle {lin_o}")
+
+
+def test_cpr_apply_overlap2_matches(dev, orc):
+    """RAS with overlap 2 (the paper's Table 9 variant): one CPR application."""
+    w = workloads.make_small()
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
+        dev, orc, w, 2, orc.cpr_opts(overlap=2), dev.cpr_opts(overlap=2))
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal(mo.N)
+    f[2 * mo.n + 1::2] = 0.0
+    zg = _h(P.apply(_t(f)))
+    zo = Po.apply(f)
+    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
