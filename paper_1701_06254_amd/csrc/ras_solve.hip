@@ -29,7 +29,8 @@
 constexpr int BS = 256;
 constexpr int WG = 1024;               // threads of a subdomain workgroup
 constexpr int NWAVE = WG / 64;
-constexpr int NCW = NWAVE;             // sweep: wavefronts sharing the slices of a level
+constexpr int SWG = 512;               // sweep workgroup: 8 wavefronts, 256 VGPRs each
+constexpr int NCW = SWG / 64;          // sweep: wavefronts sharing the slices of a level
 constexpr int MAXK = 3;                // entries per lane held in registers (two lanes per row)
 constexpr int MAXLEV = 4096;           // levels per subdomain kept in LDS
 
@@ -502,45 +503,53 @@ __device__ __forceinline__ void row_update(const Row<T> &R, const T *y0, const T
     t1 += __shfl_xor(t1, 1, 64);
 }
 
-// One step of a triangular sweep: the wavefront's current slice `cur`
-// (task tL, ts), whose static data are in registers.  It first passes the
-// workgroup barriers of every level before tL that it has not passed yet,
-// then issues the loads that depend on earlier levels (the y values of its
-// rows), then the static data of its next slice into `nxt` and the
-// metadata of the slice after that, computes and stores.  Loads retire in
-// issue order, so waiting for the current rows never waits for the
-// prefetches, and a fetch never waits for its own metadata: both were
-// requested one step earlier.  The caller alternates the two row buffers,
-// so no register copy forces a prefetch to land within its own step.
+// The next five tasks (slices) of a wavefront: tasks k .. k+4 of its walk.
+struct Tasks {
+    int L[5], s[5];
+};
+
+// One step of a triangular sweep on task k, whose static data sit in `cur`.
+// Tasks k+1 and k+2 are already being fetched into two other buffers.  The
+// step first passes the workgroup barriers of every level before task k's
+// that it has not passed yet, then issues the loads that depend on earlier
+// levels (the y values of its rows), then the metadata of task k+4, then
+// the static data of task k+3 into `fill`, computes and stores.  Loads
+// retire in issue order, so waiting for the current rows never waits for the
+// prefetches; each fetch was requested three steps before it is used, its
+// metadata four.  The caller rotates four row buffers, so no register copy
+// forces a prefetch to land early.
 template <class T, bool FWD>
 __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *soff, int nlev,
-                                           int wave, int lane, Row<T> &cur, Row<T> &nxt,
-                                           int4 &mn, int &tL, int &ts, int &nL, int &ns,
-                                           int &passed) {
+                                           int wave, int lane, Row<T> &cur, Row<T> &fill,
+                                           int4 &mfill, Tasks &q, int &passed) {
     const int dir = FWD ? 1 : -1;
     const int4 *meta = FWD ? A.mL : A.mU;
-    int rank = FWD ? tL : nlev - 1 - tL;          // levels this one waits for
+    int rank = FWD ? q.L[0] : nlev - 1 - q.L[0];  // levels this one waits for
     while (passed < rank) {
         __syncthreads();
         passed++;
     }
-    int n2L = nL, n2s = ns;
-    next_task(soff, nlev, dir, wave, n2L, n2s);
-    n2L = __builtin_amdgcn_readfirstlane(n2L);
-    n2s = __builtin_amdgcn_readfirstlane(n2s);
+    int L5 = q.L[4], s5 = q.s[4];
+    next_task(soff, nlev, dir, wave, L5, s5);
+    L5 = __builtin_amdgcn_readfirstlane(L5);
+    s5 = __builtin_amdgcn_readfirstlane(s5);
     T y0[MAXK], y1[MAXK];
 #pragma unroll
     for (int k = 0; k < MAXK; k++) {
         // a column outside y (never produced by the set-up) is read as the
         // row itself rather than out of bounds
-        long q = cur.h + 2 * k < cur.n ? cur.col[k] : cur.p;
-        q = (unsigned long)q < (unsigned long)A.mtot ? q : (long)cur.p;
-        y0[k] = A.y[2 * q];
-        y1[k] = A.y[2 * q + 1];
+        long qc = cur.h + 2 * k < cur.n ? cur.col[k] : cur.p;
+        qc = (unsigned long)qc < (unsigned long)A.mtot ? qc : (long)cur.p;
+        y0[k] = A.y[2 * qc];
+        y1[k] = A.y[2 * qc + 1];
     }
     __builtin_amdgcn_sched_barrier(0);
-    fetch_row<T, FWD>(nxt, A, mn, ns >= 0, lane);
-    mn = load_meta(meta, n2s);
+    // the metadata of task k+4 goes out before the fetch of task k+3, so the
+    // next step's wait for it does not wait for that fetch as well
+    int4 mnext = load_meta(meta, q.s[4]);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_row<T, FWD>(fill, A, mfill, q.s[3] >= 0, lane);
+    mfill = mnext;
     // keep every load above issued before any use of the y values
     __builtin_amdgcn_sched_barrier(0);
     T t0, t1;
@@ -557,10 +566,13 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *sof
             A.y[2 * (long)cur.p + 1] = cur.d[2] * t0 + cur.d[3] * t1;
         }
     }
-    tL = nL;
-    ts = ns;
-    nL = n2L;
-    ns = n2s;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        q.L[i] = q.L[i + 1];
+        q.s[i] = q.s[i + 1];
+    }
+    q.L[4] = L5;
+    q.s[4] = s5;
 }
 
 // One triangular sweep of a subdomain: forward (L, unit diagonal) or
@@ -572,22 +584,28 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *soff
                                           int wave, int lane) {
     const int dir = FWD ? 1 : -1;
     const int4 *meta = FWD ? A.mL : A.mU;
-    int tL = FWD ? -1 : nlev, ts = -1;
-    next_task(soff, nlev, dir, wave, tL, ts);
-    tL = __builtin_amdgcn_readfirstlane(tL);
-    ts = __builtin_amdgcn_readfirstlane(ts);
-    int nL = tL, ns = ts;
-    next_task(soff, nlev, dir, wave, nL, ns);
-    nL = __builtin_amdgcn_readfirstlane(nL);
-    ns = __builtin_amdgcn_readfirstlane(ns);
-    Row<T> ra, rb;
-    fetch_row<T, FWD>(ra, A, load_meta(meta, ts), ts >= 0, lane);
-    int4 mn = load_meta(meta, ns);
+    Tasks q;
+    int L = FWD ? -1 : nlev, sl = -1;
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        next_task(soff, nlev, dir, wave, L, sl);
+        q.L[i] = L = __builtin_amdgcn_readfirstlane(L);
+        q.s[i] = sl = __builtin_amdgcn_readfirstlane(sl);
+    }
+    Row<T> b0, b1, b2, b3;
+    fetch_row<T, FWD>(b0, A, load_meta(meta, q.s[0]), q.s[0] >= 0, lane);
+    fetch_row<T, FWD>(b1, A, load_meta(meta, q.s[1]), q.s[1] >= 0, lane);
+    fetch_row<T, FWD>(b2, A, load_meta(meta, q.s[2]), q.s[2] >= 0, lane);
+    int4 mfill = load_meta(meta, q.s[3]);
     int passed = 0;
-    while (ts >= 0) {
-        sweep_step<T, FWD>(A, soff, nlev, wave, lane, ra, rb, mn, tL, ts, nL, ns, passed);
-        if (ts < 0) break;
-        sweep_step<T, FWD>(A, soff, nlev, wave, lane, rb, ra, mn, tL, ts, nL, ns, passed);
+    while (q.s[0] >= 0) {
+        sweep_step<T, FWD>(A, soff, nlev, wave, lane, b0, b3, mfill, q, passed);
+        if (q.s[0] < 0) break;
+        sweep_step<T, FWD>(A, soff, nlev, wave, lane, b1, b0, mfill, q, passed);
+        if (q.s[0] < 0) break;
+        sweep_step<T, FWD>(A, soff, nlev, wave, lane, b2, b1, mfill, q, passed);
+        if (q.s[0] < 0) break;
+        sweep_step<T, FWD>(A, soff, nlev, wave, lane, b3, b2, mfill, q, passed);
     }
     while (passed < nlev) {
         __syncthreads();
@@ -598,11 +616,11 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *soff
 // Forward then backward substitution of one subdomain per workgroup on the
 // gathered right-hand side; the result overwrites y in local order.
 template <class T>
-__global__ __launch_bounds__(WG) void k_ras_sweep(SweepArgs<T> A) {
+__global__ __launch_bounds__(SWG) void k_ras_sweep(SweepArgs<T> A) {
     __shared__ int soff[MAXLEV + 1];
     int s = blockIdx.x;
     int nlev = A.nlev[s], base = A.lbase[s];
-    for (int L = threadIdx.x; L <= nlev; L += WG) soff[L] = A.soff[base + L];
+    for (int L = threadIdx.x; L <= nlev; L += SWG) soff[L] = A.soff[base + L];
     __syncthreads();
     int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
@@ -815,7 +833,7 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     A.nl = D.nl.p; A.nu = D.nu.p; A.lcol = D.lcol.p; A.ucol = D.ucol.p;
     A.lval = F.lval.p; A.uval = F.uval.p; A.dinv = F.dinv.p; A.rl = rl; A.y = y;
     A.mtot = mtot;
-    k_ras_sweep<T><<<P->rs.ns, WG, 0, s>>>(A);
+    k_ras_sweep<T><<<P->rs.ns, SWG, 0, s>>>(A);
     R2P_LAUNCH();
     k_ras_scatter<T><<<nb, BS, 0, s>>>(mtot, P->J->m->ph.n, D.glob.p, D.owned.p, y, xp,
                                        accumulate, out);
