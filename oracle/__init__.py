@@ -128,9 +128,11 @@ def lib():
     L.om_api_amg_h_vcycle.argtypes = [vp, f64p, f64p]
     L.om_fgmres.argtypes = [C.POINTER(Bsr), vp, f64p, f64p, C.c_int, C.c_double, C.c_int,
                             C.POINTER(C.c_int), C.POINTER(C.c_double), vp]
+    L.om_bicgstab.argtypes = [C.POINTER(Bsr), vp, f64p, f64p, C.c_double, C.c_int,
+                              C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.om_newton_step.argtypes = [vp, f64p, C.c_double, C.POINTER(CprOpts), C.c_int, C.c_double,
                                  C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double,
-                                 C.POINTER(C.c_int), C.POINTER(C.c_int), f64p]
+                                 C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), f64p]
     _lib = L
     return L
 
@@ -283,7 +285,7 @@ class Model:
         return ph
 
     def newton_step(self, x, dt, opts=None, restart=30, rtol=1e-8, maxit=300, ntol=1e-8,
-                    max_newton=20, exact_linear=False, forcing=0, ds_max=0.2):
+                    max_newton=20, exact_linear=False, forcing=0, ds_max=0.2, krylov=0):
         """One implicit step in place; returns (status, newton_its, linear_its, hist)."""
         opts = cpr_opts() if opts is None else opts
         xx = _f64(x).copy()
@@ -291,7 +293,7 @@ class Model:
         hist = np.zeros(max_newton + 1)
         rc = lib().om_newton_step(self.h, xx, float(dt), C.byref(opts), restart, rtol, maxit,
                                   ntol, max_newton, int(exact_linear), int(forcing),
-                                  float(ds_max), C.byref(ni), C.byref(li), hist)
+                                  float(ds_max), int(krylov), C.byref(ni), C.byref(li), hist)
         if rc == 0:
             x[:] = xx
         return rc, ni.value, li.value, hist[:ni.value + 1]
@@ -483,6 +485,15 @@ class Cpr:
         y = np.zeros(len(r))
         lib().om_api_ras_apply(self.h, _f64(r), y)
         return y
+
+
+def bicgstab(A, b, P=None, rtol=1e-8, maxit=300):
+    """Right-preconditioned BiCGSTAB from zero; returns (x, status, iters, relres)."""
+    x = np.zeros(len(b))
+    its, rr = C.c_int(), C.c_double()
+    st = lib().om_bicgstab(C.byref(A.cstruct()), None if P is None else P.h, _f64(b), x, rtol,
+                           maxit, C.byref(its), C.byref(rr))
+    return x, st, its.value, rr.value
 
 
 def fgmres(A, b, P=None, restart=30, rtol=1e-8, maxit=300, history=False):

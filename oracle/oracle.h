@@ -175,9 +175,12 @@ void om_cpr_apply(const om_cpr *P, const double *f, double *x);
 void om_cpr_free(om_cpr *P);
 int  om_fgmres(const om_bsr *A, const om_cpr *P, const double *b, double *x, int restart,
                double rtol, int maxit, int *iters, double *relres, double *hist);
+int  om_bicgstab(const om_bsr *A, const om_cpr *P, const double *b, double *x, double rtol,
+                 int maxit, int *iters, double *relres);
+/* krylov: 0 FGMRES(restart), 1 BiCGSTAB */
 int  om_newton_step(const om_model *m, double *x, double dt, const om_cpr_opts *o, int restart,
                     double rtol, int maxit, double ntol, int max_newton, int exact_linear,
-                    int forcing, double ds_max, int *newton_its, int *lin_its,
+                    int forcing, double ds_max, int krylov, int *newton_its, int *lin_its,
                     double *res_hist);
 
 #ifdef __cplusplus

@@ -204,16 +204,95 @@ done:
     return status;
 }
 
+/* Right-preconditioned BiCGSTAB (van der Vorst's stabilised bi-conjugate
+ * gradients, the paper's other Krylov solver), zero initial guess, shadow
+ * residual r^ = b.  Converged when the recursive residual is at most rtol
+ * ||b||; the true residual b - A x is then checked, and if it is above the
+ * target the recurrences restart from it.  One iteration = two
+ * preconditioner applications and two products with A. */
+int om_bicgstab(const om_bsr *A, const om_cpr *P, const double *b, double *x, double rtol,
+                int maxit, int *iters, double *relres)
+{
+    int N = 2 * A->nb;
+    double *r = (double *)malloc(sizeof(double) * N), *rh = (double *)malloc(sizeof(double) * N);
+    double *p = (double *)calloc(N, sizeof(double)), *v = (double *)calloc(N, sizeof(double));
+    double *ph = (double *)malloc(sizeof(double) * N), *sv = (double *)malloc(sizeof(double) * N);
+    double *sh = (double *)malloc(sizeof(double) * N), *t = (double *)malloc(sizeof(double) * N);
+    for (int i = 0; i < N; i++) x[i] = 0.0;
+    double bnorm = nrm2(N, b);
+    int status = 1, it = 0;
+    *iters = 0;
+    *relres = 0.0;
+    if (bnorm == 0.0) { status = 0; goto done; }
+    memcpy(r, b, sizeof(double) * N);
+    memcpy(rh, b, sizeof(double) * N);
+    double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+    int fresh = 1;
+    while (it < maxit) {
+        double rho = om_dot(N, rh, r);
+        if (rho == 0.0) { status = 2; break; }
+        if (fresh) {
+            memcpy(p, r, sizeof(double) * N);
+        } else {
+            double beta = (rho / rho_prev) * (alpha / omega);
+            for (int i = 0; i < N; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        }
+        fresh = 0;
+        if (P) om_cpr_apply(P, p, ph); else memcpy(ph, p, sizeof(double) * N);
+        om_bsr_spmv(A, ph, v);
+        double rv = om_dot(N, rh, v);
+        if (rv == 0.0) { status = 2; break; }
+        alpha = rho / rv;
+        for (int i = 0; i < N; i++) sv[i] = r[i] - alpha * v[i];
+        it++;
+        int conv = 0;
+        if (nrm2(N, sv) <= rtol * bnorm) {
+            for (int i = 0; i < N; i++) x[i] += alpha * ph[i];
+            conv = 1;
+        } else {
+            if (P) om_cpr_apply(P, sv, sh); else memcpy(sh, sv, sizeof(double) * N);
+            om_bsr_spmv(A, sh, t);
+            double tt = om_dot(N, t, t);
+            omega = tt > 0.0 ? om_dot(N, t, sv) / tt : 0.0;
+            for (int i = 0; i < N; i++) x[i] += alpha * ph[i] + omega * sh[i];
+            for (int i = 0; i < N; i++) r[i] = sv[i] - omega * t[i];
+            rho_prev = rho;
+            if (nrm2(N, r) <= rtol * bnorm) conv = 1;
+            else if (omega == 0.0) { status = 2; break; }
+        }
+        if (conv) {
+            om_bsr_spmv(A, x, t);                                  /* true residual */
+            for (int i = 0; i < N; i++) r[i] = b[i] - t[i];
+            double rn = nrm2(N, r);
+            *relres = rn / bnorm;
+            if (rn <= rtol * bnorm) { status = 0; break; }
+            memcpy(rh, r, sizeof(double) * N);                     /* restart */
+            rho_prev = alpha = omega = 1.0;
+            fresh = 1;
+        }
+    }
+    if (status != 0) {
+        om_bsr_spmv(A, x, t);
+        for (int i = 0; i < N; i++) r[i] = b[i] - t[i];
+        *relres = nrm2(N, r) / bnorm;
+    }
+done:
+    *iters = it;
+    free(r); free(rh); free(p); free(v); free(ph); free(sv); free(sh); free(t);
+    return status;
+}
+
 /* One implicit time step x^n -> x^{n+1} by Newton's method (in place).
  * forcing 0: every linear solve to rtol; forcing 1: Eisenstat-Walker
  * (second choice of Eq 26, clipped to [0.01, 0.1], starting at 0.1).
- * exact_linear: solve each Newton system by dense LU instead of CPR-FGMRES.
+ * exact_linear: solve each Newton system by dense LU instead of CPR-Krylov;
+ * krylov 0: FGMRES(restart), 1: BiCGSTAB.
  * ds_max > 0 limits each cell's saturation change per Newton iteration.
  * Returns 0 on convergence (x updated), 1 if Newton or a linear solve
  * failed (x unchanged). */
 int om_newton_step(const om_model *m, double *x, double dt, const om_cpr_opts *o, int restart,
                    double rtol, int maxit, double ntol, int max_newton, int exact_linear,
-                   int forcing, double ds_max, int *newton_its, int *lin_its,
+                   int forcing, double ds_max, int krylov, int *newton_its, int *lin_its,
                    double *res_hist)
 {
     int n = m->n, N = 2 * (m->n + m->nw);
@@ -263,7 +342,8 @@ int om_newton_step(const om_model *m, double *x, double dt, const om_cpr_opts *o
             om_cpr P;
             int rc = om_cpr_setup(&P, &Ad, m, xk, o);
             int its = 0; double rr = 0.0;
-            if (!rc) rc = om_fgmres(&Ad, &P, bd, y, restart, tol, maxit, &its, &rr, NULL);
+            if (!rc) rc = krylov == 1 ? om_bicgstab(&Ad, &P, bd, y, tol, maxit, &its, &rr)
+                                      : om_fgmres(&Ad, &P, bd, y, restart, tol, maxit, &its, &rr, NULL);
             lits += its;
             om_cpr_free(&P);
             om_bsr_free(&Ad);

@@ -287,6 +287,33 @@ def test_fgmres_cpr_matches_dense_lu(oracle_lib, form):
     assert np.linalg.norm(y - yd) <= kappa * 1e-8 * np.linalg.norm(yd)
 
 
+@pytest.mark.parametrize("form", [0, 1])
+def test_bicgstab_cpr_matches_dense_lu(oracle_lib, form):
+    """BiCGSTAB + CPR on the same 66-unknown system: true relative residual
+    at most 1e-8 and the dense-LU solution within kappa * 1e-8."""
+    w = workloads.make_tiny()
+    m, x, J, b = _system(oracle_lib, w, steps=2, dt=5.0)
+    Ad, bd = oracle_lib.decouple(J, b, m.n, oracle_lib.DEC_QI)
+    P = oracle_lib.Cpr(Ad, m, x, oracle_lib.cpr_opts(form=form, px=2, py=2))
+    y, st, its, rr = oracle_lib.bicgstab(Ad, bd, P)
+    A = Ad.to_dense()
+    assert st == 0 and rr <= 1e-8
+    assert np.linalg.norm(bd - A @ y) <= 1e-8 * np.linalg.norm(bd)
+    yd = np.linalg.solve(A, bd)
+    assert np.linalg.norm(y - yd) <= np.linalg.cond(A) * 1e-8 * np.linalg.norm(yd)
+
+
+def test_bicgstab_with_exact_preconditioner_takes_one_step(oracle_lib):
+    """With the CPR stages replaced by exact solves, M = A^-1, BiCGSTAB
+    converges in one iteration (the first half-step already solves)."""
+    w = workloads.make_tiny()
+    m, x, J, b = _system(oracle_lib, w, steps=1, dt=5.0)
+    Ad, bd = oracle_lib.decouple(J, b, m.n, oracle_lib.DEC_QI)
+    P = oracle_lib.Cpr(Ad, m, x, oracle_lib.cpr_opts(px=2, py=2, exact_stages=1))
+    y, st, its, rr = oracle_lib.bicgstab(Ad, bd, P)
+    assert st == 0 and its == 1
+
+
 def test_gmres_residual_monotone_and_identity(oracle_lib):
     w = workloads.make_small()
     m, x, J, b = _system(oracle_lib, w, steps=2)
