@@ -101,10 +101,13 @@ typedef struct {
     int precision;     /* R2P_FP64, or R2P_FP32: AMG and ILU stored and applied in FP32 */
 } r2p_cpr_opts;
 
+enum { R2P_KRYLOV_FGMRES = 0, R2P_KRYLOV_BICGSTAB = 1 };
 typedef struct {
     int restart;       /* FGMRES restart length m (1..64) */
     int maxit;         /* iteration limit */
     double rtol;       /* relative residual target on the decoupled system */
+    int method;        /* R2P_KRYLOV_FGMRES, or R2P_KRYLOV_BICGSTAB (right-preconditioned,
+                          zero start; one iteration = two CPR applications) */
 } r2p_solve_opts;
 
 typedef struct {
@@ -236,6 +239,11 @@ int r2p_ras_export(r2p_cpr *P, int s, int *glob_host, int *level_host, unsigned 
  * preconditioned flexible GMRES(restart) from y = 0 with the CPR
  * preconditioner P.  Classical Gram-Schmidt with a selective second pass;
  * convergence on the true residual of the decoupled system.
+ * o->method = R2P_KRYLOV_BICGSTAB instead runs right-preconditioned
+ * BiCGSTAB (the second Krylov solver of the numerical experiments, two CPR
+ * applications per iteration) from y = 0 with shadow residual D^-1 b;
+ * on convergence of the recursive residual the true one is checked and the
+ * method restarts from it if it is above the target.
  * Synchronous.  Returns 0, R2P_NOT_CONVERGED (y holds the last iterate) or
  * R2P_BREAKDOWN, or an error. */
 int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y,

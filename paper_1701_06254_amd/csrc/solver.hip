@@ -122,6 +122,25 @@ __global__ __launch_bounds__(BS) void k_maxpy(const double *Z, long ld, int nv, 
     x[i] = t;
 }
 
+// out = x + a y (+ b z): the BiCGSTAB updates s = r - alpha v,
+// x += alpha p^ + omega s^, r = s - omega t (out may alias x).
+__global__ __launch_bounds__(BS) void k_axpbypz(long N, const double *x, double a, const double *y,
+                                                double b, const double *z, double *out) {
+    long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i >= N) return;
+    double v = x[i] + a * y[i];
+    if (z) v = x[i] + (a * y[i] + b * z[i]);
+    out[i] = v;
+}
+
+// p = r + beta (p - omega v)
+__global__ __launch_bounds__(BS) void k_bicg_p(long N, const double *r, const double *v, double beta,
+                                               double omega, double *p) {
+    long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i >= N) return;
+    p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
 // r_orig = D (r_dec) per cell row: the residual of the undecoupled system.
 __global__ void k_undecouple(int n, long N, const double4 *dec, const double *rd, double *r) {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
@@ -253,12 +272,96 @@ static Krylov &krylov_for(r2p_cpr *P) {
     return *K;
 }
 
+// Right-preconditioned BiCGSTAB on the decoupled system (the paper's other
+// Krylov solver), from zero, shadow residual r^ = b.  Converged when the
+// recursive residual reaches rtol ||b||; the true residual is then checked
+// and, if it is above the target, the recurrences restart from it.  Dots
+// are the fused multi-dot (fixed-order reduction), read back per use.
+static int solve_bicgstab(r2p_jacobian *J, r2p_cpr *P, Krylov &K, double bnorm, double *y,
+                          const r2p_solve_opts *o, r2p_solve_info &inf, int &status,
+                          hipStream_t s) {
+    const Phys &ph = J->m->ph;
+    long N = 2L * (ph.n + ph.nw);
+    R2P_TRY(K.V.ensure((size_t)8 * N));
+    double *r = K.V.p, *rh = r + N, *p = rh + N, *v = p + N, *pp = v + N, *sv = pp + N,
+           *sp = sv + N, *t = sp + N;
+    int nb = r2p_blocks(N, BS);
+    R2P_HIP(hipMemcpyAsync(r, K.bd.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    R2P_HIP(hipMemcpyAsync(rh, K.bd.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    R2P_HIP(hipMemsetAsync(p, 0, sizeof(double) * N, s));
+    R2P_HIP(hipMemsetAsync(v, 0, sizeof(double) * N, s));
+    double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+    bool fresh = true;
+    int it = 0;
+    status = R2P_NOT_CONVERGED;
+    while (it < o->maxit) {
+        double h[2];
+        R2P_TRY(mdot(K, rh, 1, r, N, s, h));
+        double rho = h[0];
+        if (rho == 0.0 || rho != rho) { status = R2P_BREAKDOWN; break; }
+        if (fresh) {
+            R2P_HIP(hipMemcpyAsync(p, r, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        } else {
+            double beta = (rho / rho_prev) * (alpha / omega);
+            k_bicg_p<<<nb, BS, 0, s>>>(N, r, v, beta, omega, p);
+            R2P_LAUNCH();
+        }
+        fresh = false;
+        R2P_TRY(r2p_cpr_apply_impl(P, p, pp, s));
+        R2P_TRY(r2p_spmv_impl(J, pp, v, nullptr, s));
+        R2P_TRY(mdot(K, rh, 1, v, N, s, h));
+        if (h[0] == 0.0 || h[0] != h[0]) { status = R2P_BREAKDOWN; break; }
+        alpha = rho / h[0];
+        k_axpbypz<<<nb, BS, 0, s>>>(N, r, -alpha, v, 0.0, nullptr, sv);
+        R2P_LAUNCH();
+        it++;
+        R2P_TRY(mdot(K, nullptr, 0, sv, N, s, h));
+        bool conv = false;
+        if (sqrt(h[0]) <= o->rtol * bnorm) {
+            k_axpbypz<<<nb, BS, 0, s>>>(N, y, alpha, pp, 0.0, nullptr, y);
+            R2P_LAUNCH();
+            conv = true;
+        } else {
+            R2P_TRY(r2p_cpr_apply_impl(P, sv, sp, s));
+            R2P_TRY(r2p_spmv_impl(J, sp, t, nullptr, s));
+            R2P_TRY(mdot(K, sv, 1, t, N, s, h));          // h[0] = t.s, h[1] = t.t
+            omega = h[1] > 0.0 ? h[0] / h[1] : 0.0;
+            k_axpbypz<<<nb, BS, 0, s>>>(N, y, alpha, pp, omega, sp, y);
+            R2P_LAUNCH();
+            k_axpbypz<<<nb, BS, 0, s>>>(N, sv, -omega, t, 0.0, nullptr, r);
+            R2P_LAUNCH();
+            rho_prev = rho;
+            R2P_TRY(mdot(K, nullptr, 0, r, N, s, h));
+            if (sqrt(h[0]) <= o->rtol * bnorm) conv = true;
+            else if (omega == 0.0) { status = R2P_BREAKDOWN; break; }
+        }
+        if (conv) {
+            R2P_TRY(r2p_spmv_impl(J, y, r, K.bd.p, s));  // true residual bd - A y
+            R2P_TRY(mdot(K, nullptr, 0, r, N, s, h));
+            inf.relres = sqrt(h[0]) / bnorm;
+            if (sqrt(h[0]) <= o->rtol * bnorm) { status = 0; break; }
+            R2P_HIP(hipMemcpyAsync(rh, r, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+            rho_prev = alpha = omega = 1.0;
+            fresh = true;
+        }
+    }
+    if (status != 0) {
+        double h[2];
+        R2P_TRY(r2p_spmv_impl(J, y, r, K.bd.p, s));
+        R2P_TRY(mdot(K, nullptr, 0, r, N, s, h));
+        inf.relres = sqrt(h[0]) / bnorm;
+    }
+    inf.iterations = it;
+    return 0;
+}
+
 extern "C" int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y,
                          const r2p_solve_opts *o, r2p_solve_info *info, void *stream) {
     auto t0 = std::chrono::steady_clock::now();
     if (!J || !P || !b || !y || !o) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
     if (!P->ready || P->J != J || J->state != 2) { r2p_set_error("CPR not set up for this Jacobian"); return R2P_ESTATE; }
-    if (o->restart < 1 || o->restart > 64 || o->maxit < 1 || !(o->rtol > 0)) {
+    if (o->restart < 1 || o->restart > 64 || o->maxit < 1 || !(o->rtol > 0) ||
+        (o->method != R2P_KRYLOV_FGMRES && o->method != R2P_KRYLOV_BICGSTAB)) {
         r2p_set_error("invalid solve options");
         return R2P_EINVAL;
     }
@@ -288,6 +391,8 @@ extern "C" int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y
     if (bnorm == 0.0) {
         status = 0;
         inf.relres = 0.0;
+    } else if (o->method == R2P_KRYLOV_BICGSTAB) {
+        R2P_TRY(solve_bicgstab(J, P, K, bnorm, y, o, inf, status, s));
     } else {
         std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m);
         R2P_HIP(hipMemcpyAsync(K.r.p, K.bd.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
@@ -402,6 +507,7 @@ extern "C" void r2p_default_newton_opts(r2p_newton_opts *o) {
     o->lin.restart = 30;
     o->lin.maxit = 300;
     o->lin.rtol = 1e-8;
+    o->lin.method = R2P_KRYLOV_FGMRES;
     o->guess_rule = R2P_GUESS_SCALED_INF;
 }
 

@@ -49,7 +49,8 @@ class CprOpts(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double)]
+    _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double),
+                ("method", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -77,8 +78,11 @@ def cpr_opts(decouple=DEC_QI, order=ORDER_POTENTIAL, form=CPR_TWO_STAGE, px=4, p
                    match_rounds, agg_passes, precision)
 
 
-def solve_opts(restart=30, maxit=300, rtol=1e-8):
-    return SolveOpts(restart, maxit, rtol)
+KRYLOV_FGMRES, KRYLOV_BICGSTAB = 0, 1
+
+
+def solve_opts(restart=30, maxit=300, rtol=1e-8, method=KRYLOV_FGMRES):
+    return SolveOpts(restart, maxit, rtol, method)
 
 
 GUESS_SCALED_INF, GUESS_L2, GUESS_TRY = 0, 1, 2
@@ -377,7 +381,7 @@ class Cpr:
 
 
 def solve(J, P, b, opts=None, y=None):
-    """Solve J y = b with CPR-FGMRES; returns (y, SolveInfo)."""
+    """Solve J y = b with CPR-FGMRES or CPR-BiCGSTAB (opts.method); returns (y, SolveInfo)."""
     y = J.model.tensor() if y is None else y
     info = SolveInfo()
     o = solve_opts() if opts is None else opts

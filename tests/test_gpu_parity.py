@@ -238,6 +238,24 @@ def test_fgmres_solve_matches(dev, orc, form):
     assert np.linalg.norm(bd - A @ yg) <= 1.000001e-8 * np.linalg.norm(bd)
 
 
+@pytest.mark.parametrize("form", [0, 1])
+def test_bicgstab_solve_matches(dev, orc, form):
+    """BiCGSTAB (two CPR applications per iteration) on the same system: the
+    true relative residual of the device solution at most 1e-8, and the
+    iteration count within 2 of the oracle's."""
+    w = workloads.make_small()
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
+        dev, orc, w, 3, orc.cpr_opts(form=form), dev.cpr_opts(form=form))
+    yo, st, its_o, rr_o = orc.bicgstab(Ad, bd, Po)
+    assert st == 0
+    yg, info = dev.solve(J, P, b, dev.solve_opts(method=dev.KRYLOV_BICGSTAB))
+    assert info.status == 0 and info.relres <= 1e-8
+    assert abs(info.iterations - its_o) <= 2, (info.iterations, its_o)
+    A = Ad.to_scipy()
+    assert np.linalg.norm(bd - A @ _h(yg)) <= 1.000001e-8 * np.linalg.norm(bd)
+    print(f"BiCGSTAB form {form}: iterations GPU {info.iterations}, oracle {its_o}")
+
+
 def test_newton_steps_match_oracle(dev, orc):
     """Quarter five-spot (2,000 cells), 10 steps of 10 days: fields within
     1e-6 relative 2-norm of the oracle on p and s_w."""
@@ -276,12 +294,13 @@ def test_fp32_preconditioner_apply_close_to_oracle(dev, orc):
     assert err <= 1e-4
 
 
-@pytest.mark.parametrize("variant", ["fp32", "ew", "abf"])
+@pytest.mark.parametrize("variant", ["fp32", "ew", "abf", "bicgstab"])
 def test_newton_variants_match_oracle(dev, orc, variant):
     """The same 10 steps with the FP32 preconditioner, with Eisenstat-Walker
-    forcing (Eq 26, second choice) and with ABF decoupling: the Newton test
-    fixes the fields, so each must stay within 1e-6 of the FP64 oracle run
-    with the same options (FP32: the standard FP64 oracle)."""
+    forcing (Eq 26, second choice), with ABF decoupling and with BiCGSTAB as
+    the Krylov solver: the Newton test fixes the fields, so each must stay
+    within 1e-6 of the FP64 oracle run with the same options (FP32: the
+    standard FP64 oracle)."""
     w = workloads.make_small()
     n = w["grid"]["n"]
     mo = orc.Model(w)
@@ -294,12 +313,16 @@ def test_newton_variants_match_oracle(dev, orc, variant):
     elif variant == "ew":
         go = dev.newton_opts(forcing=dev.FORCING_EW)
         oo, forcing = orc.cpr_opts(), 1
-    else:
+    elif variant == "abf":
         go = dev.newton_opts(cpr=dev.cpr_opts(decouple=dev.DEC_ABF))
         oo, forcing = orc.cpr_opts(decouple=orc.DEC_ABF), 0
+    else:
+        go = dev.newton_opts(lin=dev.solve_opts(method=dev.KRYLOV_BICGSTAB))
+        oo, forcing = orc.cpr_opts(), 0
+    krylov = 1 if variant == "bicgstab" else 0
     lin_g = lin_o = 0
     for step in range(w["steps"]):
-        rc, ni, li, _ = mo.newton_step(xo, w["dt"], oo, forcing=forcing)
+        rc, ni, li, _ = mo.newton_step(xo, w["dt"], oo, forcing=forcing, krylov=krylov)
         assert rc == 0
         info = mg.newton_step(xg, w["dt"], go)
         assert info.status == 0
