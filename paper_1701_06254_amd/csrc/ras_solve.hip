@@ -9,16 +9,19 @@
 // successors stay in local order, so every block update happens in the same
 // sequence as a sequential ILU(0) in that order and the factors match it.
 //
-// One workgroup (16 wavefronts) processes one subdomain level by level, a
-// workgroup barrier between levels; a wavefront takes a slice of 32 rows,
-// two lanes per row (each lane takes every other block of the row, so the
-// six couplings of a grid cell stay in registers).  Levels are a latency
-// chain, so every wavefront fetches the static data of its next slice
-// (factor blocks, columns, right-hand side) into registers right after
-// issuing the current slice's dependent loads: loads retire in issue order,
-// so waiting for the current rows never waits for the prefetch, and the
-// prefetch overlaps the compute, the store and the barrier.  The gather of the right-hand side into local order and the
-// restricted scatter of the result run as separate full-device kernels.
+// One workgroup (8 wavefronts) processes one subdomain level by level, a
+// workgroup barrier between levels; a wavefront takes a slice of 32 rows of
+// a level, two lanes per row (each lane takes every other block of the row,
+// so the six couplings of a grid cell stay in registers), and the
+// wavefronts take the slices of the subdomain in turn.  Levels are a
+// latency chain, so nothing a step waits for is requested in that step:
+// the static data of a slice (columns, factor blocks, right-hand side) are
+// requested three and four steps ahead; the y values its rows need that
+// were finished two steps earlier are requested then; the rest were
+// finished in the last few levels and are read from an LDS ring that holds
+// the results of the most recent rows.  The gather of the right-hand side
+// into local order and the restricted scatter of the result run as separate
+// full-device kernels.
 //
 // Compiled without floating-point contraction (reproducible block products).
 #include <algorithm>
@@ -398,214 +401,251 @@ __global__ void k_ras_scatter(int mtot, int n, const int *glob, const unsigned c
 
 template <class T>
 struct SweepArgs {
-    const int *lbase, *nlev, *soff;
-    const int4 *mL, *mU;         // per slice: (first position, rows, width, entry base) of L / U
-    const int *nl, *nu, *lcol, *ucol;
+    const int *lbase, *nlev, *soff, *lptr;
+    const int4 *mL, *mU;         // per slice: (first position, rows | slot pairs << 8, entry base, level)
+    const int *lcol, *ucol;
     const T *lval, *uval, *dinv, *rl;
     T *y;
     int mtot;                    // local rows over all subdomains: the extent of y
 };
 
-// A row's static data held in the registers of its two lanes: lane h of
-// the pair holds the row's entries e = h, h + 2, ... up to MAXK of them
-// (the first 2 MAXK blocks of the row between the pair), and both lanes
-// hold the row's right-hand side (forward: the gathered residual; backward:
-// the forward result) and, backward, its inverse diagonal block.  Loads are
-// unconditional (columns past a slice's width re-read its last column, or
-// the zero padding after the arrays for an empty slice) so the fetch has no
-// data-dependent branch.
+// LDS ring of the results of recently finished rows: position p sits in
+// slot p mod RING.  While level L is being computed, a finished position q
+// is still in the ring when no position written after it has the same slot.
+// Positions written after q lie in q's own level (concurrently) or in later
+// levels up to L, so with every level narrower than RING the test is
+// forward q >= end(L) - RING, backward q < start(L) + RING; with a wider
+// level the window is empty and such entries come from global memory.
+constexpr int RING_BYTES = 128 * 1024;
 template <class T>
-struct Row {
-    int p, n, base, h;
-    bool valid;
-    T a0, a1;
-    int col[MAXK];
-    T v[MAXK][4];
-    T d[4];
+struct RingSize {
+    static constexpr int rows = RING_BYTES / (2 * (int)sizeof(T));
 };
 
-// Slice metadata of task `sl` (slice 0 when there is none): one uniform
-// 16-byte vector load, so that it retires in order with the other loads.
-__device__ __forceinline__ int4 load_meta(const int4 *meta, int sl) {
-    return meta[sl < 0 ? 0 : sl];
+template <class T>
+struct Vec2 {
+    typedef T type __attribute__((ext_vector_type(2)));
+};
+template <class T>
+struct Vec4 {
+    typedef T type __attribute__((ext_vector_type(4)));
+};
+
+// The static data of one task (slice) held by the lane pair of each row:
+// lane h holds entries e = h, h + 2, h + 4 of the row (slot pairs k < MAXK),
+// component h of the right-hand side and, backward, row h of the inverse
+// diagonal block; y values of entries finished before the prefetch was
+// issued arrive in yf.  st .. L are uniform.
+template <class T>
+struct Task {
+    int st, cn, w, b, L, pf;
+    T a, d0, d1;
+    T v[MAXK][4];
+    T yf[MAXK][2];
+};
+
+// Slice of task j of a wavefront: the wavefronts take the slices of the
+// subdomain in turn (forward from the first, backward from the last).  Past
+// the wavefront's last task the last one is repeated (prefetches only).
+template <bool FWD>
+__device__ __forceinline__ int task_slice(int sa, int sb, int wave, int j, int nt) {
+    int jj = j < nt ? j : nt - 1;
+    return FWD ? sa + wave + NCW * jj : sb - 1 - wave - NCW * jj;
 }
 
 template <class T, bool FWD>
-__device__ __forceinline__ void fetch_row(Row<T> &R, const SweepArgs<T> &A, int4 m, bool task,
-                                          int lane) {
-    int st = __builtin_amdgcn_readfirstlane(m.x), cnt = __builtin_amdgcn_readfirstlane(m.y);
-    int wc = __builtin_amdgcn_readfirstlane(m.z), b = __builtin_amdgcn_readfirstlane(m.w);
-    int r = lane >> 1;
-    R.h = lane & 1;
-    R.valid = task && r < cnt;
-    int p = st + (r < cnt ? r : 0);
-    R.p = p;
-    R.base = b + lane;
-    // lanes past the slice's rows see only padding columns (-1): they take
-    // no blocks, so every column a lane dereferences is a real local row
-    int nrow = FWD ? A.nl[p] : A.nu[p];
-    R.n = R.valid ? nrow : 0;
-    if (FWD) { R.a0 = A.rl[2 * (long)p]; R.a1 = A.rl[2 * (long)p + 1]; }
-    else { R.a0 = A.y[2 * (long)p]; R.a1 = A.y[2 * (long)p + 1]; }
+__device__ __forceinline__ void load_cols(int (&c)[MAXK], const SweepArgs<T> &A, int4 m, int lane) {
+    int w = __builtin_amdgcn_readfirstlane(m.y) >> 8, b = __builtin_amdgcn_readfirstlane(m.z);
     const int *cols = FWD ? A.lcol : A.ucol;
+#pragma unroll
+    for (int k = 0; k < MAXK; k++) c[k] = k < w ? cols[(long)b + (long)k * RAS_SLICE + lane] : -1;
+}
+
+template <class T, bool FWD>
+__device__ __forceinline__ void load_task(Task<T> &R, const SweepArgs<T> &A, int4 m, int lane) {
+    typedef typename Vec4<T>::type V4;
+    typedef typename Vec2<T>::type V2;
+    R.st = __builtin_amdgcn_readfirstlane(m.x);
+    int cw = __builtin_amdgcn_readfirstlane(m.y);
+    R.cn = cw & 255;
+    R.w = cw >> 8;
+    R.b = __builtin_amdgcn_readfirstlane(m.z);
+    R.L = __builtin_amdgcn_readfirstlane(m.w);
+    int r = lane >> 1;
+    // rows past the slice's end read its last row (never stored)
+    long p = R.st + (r < R.cn ? r : R.cn - 1);
+    int h = lane & 1;
+    R.a = FWD ? A.rl[2 * p + h] : A.y[2 * p + h];
+    if (!FWD) {
+        V2 d = *(const V2 *)&A.dinv[4 * p + 2 * h];
+        R.d0 = d.x;
+        R.d1 = d.y;
+    }
     const T *vals = FWD ? A.lval : A.uval;
 #pragma unroll
     for (int k = 0; k < MAXK; k++) {
-        int kk = k < wc ? k : (wc > 0 ? wc - 1 : 0);
-        long idx = (long)R.base + (long)kk * RAS_SLICE;
-        R.col[k] = cols[idx];
-        R.v[k][0] = vals[4 * idx]; R.v[k][1] = vals[4 * idx + 1];
-        R.v[k][2] = vals[4 * idx + 2]; R.v[k][3] = vals[4 * idx + 3];
-    }
-    if (!FWD) {
-        const T *di = &A.dinv[4 * (long)p];
-        R.d[0] = di[0]; R.d[1] = di[1]; R.d[2] = di[2]; R.d[3] = di[3];
+        if (k < R.w) {
+            V4 v = *(const V4 *)&vals[4 * ((long)R.b + (long)k * RAS_SLICE + lane)];
+            R.v[k][0] = v.x; R.v[k][1] = v.y; R.v[k][2] = v.z; R.v[k][3] = v.w;
+        } else {
+            R.v[k][0] = R.v[k][1] = R.v[k][2] = R.v[k][3] = (T)0;
+        }
     }
 }
 
-// Next slice compute wavefront `wave` works on after slice `sl` of level `L` (sweeping
-// up when dir > 0, down otherwise), or level -1 / nlev when there is none.
-__device__ __forceinline__ void next_task(const int *soff, int nlev, int dir, int wave, int &L,
-                                          int &sl) {
-    if (sl >= 0 && sl + NCW < soff[L + 1]) { sl += NCW; return; }
-    for (L += dir; L >= 0 && L < nlev; L += dir)
-        if (soff[L] + wave < soff[L + 1]) { sl = soff[L] + wave; return; }
-    sl = -1;
-}
-
-// One row of a sweep, t = a - sum_e B_e y_{col_e}.  Each lane of the pair
-// subtracts its own entries (the even lane from a, the odd lane from 0),
-// the first MAXK from registers and any further ones loaded here; the two
-// partial results are then added, so both lanes hold the same t.
-template <class T>
-__device__ __forceinline__ void row_update(const Row<T> &R, const T *y0, const T *y1,
-                                           const int *cols, const T *vals, const T *y, int mtot,
-                                           T &t0, T &t1) {
-    t0 = R.h == 0 ? R.a0 : (T)0;
-    t1 = R.h == 0 ? R.a1 : (T)0;
+// Load the y values of the entries of a task whose rows were finished when
+// the prefetch is issued (forward: before position `bound`, backward: from
+// `bound` on); the task records the bound.
+template <class T, bool FWD>
+__device__ __forceinline__ void prefetch_y(Task<T> &R, const int (&c)[MAXK], const T *y, int mtot,
+                                           int bound) {
+    typedef typename Vec2<T>::type V2;
+    R.pf = bound;
 #pragma unroll
     for (int k = 0; k < MAXK; k++) {
-        T d0 = R.v[k][0] * y0[k] + R.v[k][1] * y1[k];
-        T d1 = R.v[k][2] * y0[k] + R.v[k][3] * y1[k];
-        bool on = R.h + 2 * k < R.n;
-        t0 -= on ? d0 : (T)0;
-        t1 -= on ? d1 : (T)0;
+        int q = c[k];
+        bool far = q >= 0 && q < mtot && (FWD ? q < bound : q >= bound);
+        if (far) {
+            V2 v = *(const V2 *)&y[2 * (long)q];
+            R.yf[k][0] = v.x;
+            R.yf[k][1] = v.y;
+        }
     }
-    for (int k = MAXK; R.h + 2 * k < R.n; k++) {
-        long idx = (long)R.base + (long)k * RAS_SLICE;
-        long q = cols[idx];
-        q = (unsigned long)q < (unsigned long)mtot ? q : (long)R.p;
-        T a0 = y[2 * q], a1 = y[2 * q + 1];
-        t0 -= vals[4 * idx] * a0 + vals[4 * idx + 1] * a1;
-        t1 -= vals[4 * idx + 2] * a0 + vals[4 * idx + 3] * a1;
-    }
-    t0 += __shfl_xor(t0, 1, 64);
-    t1 += __shfl_xor(t1, 1, 64);
 }
 
-// The next five tasks (slices) of a wavefront: tasks k .. k+4 of its walk.
-struct Tasks {
-    int L[5], s[5];
-};
-
-// One step of a triangular sweep on task k, whose static data sit in `cur`.
-// Tasks k+1 and k+2 are already being fetched into two other buffers.  The
-// step first passes the workgroup barriers of every level before task k's
-// that it has not passed yet, then issues the loads that depend on earlier
-// levels (the y values of its rows), then the metadata of task k+4, then
-// the static data of task k+3 into `fill`, computes and stores.  Loads
-// retire in issue order, so waiting for the current rows never waits for the
-// prefetches; each fetch was requested three steps before it is used, its
-// metadata four.  The caller rotates four row buffers, so no register copy
-// forces a prefetch to land early.
-template <class T, bool FWD>
-__device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *soff, int nlev,
-                                           int wave, int lane, Row<T> &cur, Row<T> &fill,
-                                           int4 &mfill, Tasks &q, int &passed) {
-    const int dir = FWD ? 1 : -1;
+// One step of a triangular sweep: task k of the wavefront (buffers U).
+// The task's level barriers come first; then, with every earlier level
+// finished, the y values of task k+2's finished entries are requested,
+// task k's other entries are read from the ring (or, outside it, from
+// global memory), and the metadata of task k+6, the columns of task k+4 and
+// the values of task k+3 are requested; task k is then computed and its
+// rows stored to y and the ring.  Every buffer is filled several steps
+// before its use, so the waits of a step are for loads issued two or more
+// steps earlier.
+template <class T, bool FWD, int U>
+__device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp, T *ring, int win,
+                                           int sa, int sb, int nlev, int wave, int lane, int nt, int k,
+                                           Task<T> (&B)[4], int (&C)[4][MAXK], int4 (&M)[4],
+                                           int &passed) {
+    typedef typename Vec2<T>::type V2;
+    constexpr int R = RingSize<T>::rows;
     const int4 *meta = FWD ? A.mL : A.mU;
-    int rank = FWD ? q.L[0] : nlev - 1 - q.L[0];  // levels this one waits for
+    Task<T> &cur = B[U];
+    int rank = FWD ? cur.L : nlev - 1 - cur.L;
     while (passed < rank) {
         __syncthreads();
         passed++;
     }
-    int L5 = q.L[4], s5 = q.s[4];
-    next_task(soff, nlev, dir, wave, L5, s5);
-    L5 = __builtin_amdgcn_readfirstlane(L5);
-    s5 = __builtin_amdgcn_readfirstlane(s5);
+    int lo = lp[cur.L], hi = lp[cur.L + 1];
+    // entries of task k+2 finished by now
+    prefetch_y<T, FWD>(B[(U + 2) & 3], C[(U + 2) & 3], A.y, A.mtot, FWD ? lo : hi);
+    // task k's entries not prefetched: from the ring, else from y
     T y0[MAXK], y1[MAXK];
+    bool on[MAXK];
+    bool slow = false;
 #pragma unroll
-    for (int k = 0; k < MAXK; k++) {
-        // a column outside y (never produced by the set-up) is read as the
-        // row itself rather than out of bounds
-        long qc = cur.h + 2 * k < cur.n ? cur.col[k] : cur.p;
-        qc = (unsigned long)qc < (unsigned long)A.mtot ? qc : (long)cur.p;
-        y0[k] = A.y[2 * qc];
-        y1[k] = A.y[2 * qc + 1];
+    for (int kk = 0; kk < MAXK; kk++) {
+        int q = C[U][kk];
+        on[kk] = q >= 0 && q < A.mtot;
+        bool pre = FWD ? q < cur.pf : q >= cur.pf;
+        V2 rv = *(const V2 *)&ring[2 * (q & (R - 1))];
+        y0[kk] = pre ? cur.yf[kk][0] : rv.x;
+        y1[kk] = pre ? cur.yf[kk][1] : rv.y;
+        bool inwin = FWD ? q >= hi - win : q < lo + win;
+        slow |= on[kk] && !pre && !inwin;
     }
-    __builtin_amdgcn_sched_barrier(0);
-    // the metadata of task k+4 goes out before the fetch of task k+3, so the
-    // next step's wait for it does not wait for that fetch as well
-    int4 mnext = load_meta(meta, q.s[4]);
-    __builtin_amdgcn_sched_barrier(0);
-    fetch_row<T, FWD>(fill, A, mfill, q.s[3] >= 0, lane);
-    mfill = mnext;
-    // keep every load above issued before any use of the y values
-    __builtin_amdgcn_sched_barrier(0);
-    T t0, t1;
-    if (FWD) {
-        row_update(cur, y0, y1, A.lcol, A.lval, A.y, A.mtot, t0, t1);
-        if (cur.valid && cur.h == 0) {
-            A.y[2 * (long)cur.p] = t0;
-            A.y[2 * (long)cur.p + 1] = t1;
-        }
-    } else {
-        row_update(cur, y0, y1, A.ucol, A.uval, A.y, A.mtot, t0, t1);
-        if (cur.valid && cur.h == 0) {
-            A.y[2 * (long)cur.p] = cur.d[0] * t0 + cur.d[1] * t1;
-            A.y[2 * (long)cur.p + 1] = cur.d[2] * t0 + cur.d[3] * t1;
+    if (__builtin_amdgcn_read_exec() & __ballot(slow)) {
+#pragma unroll
+        for (int kk = 0; kk < MAXK; kk++) {
+            int q = C[U][kk];
+            bool pre = FWD ? q < cur.pf : q >= cur.pf;
+            bool inwin = FWD ? q >= hi - win : q < lo + win;
+            if (on[kk] && !pre && !inwin) {
+                V2 v = *(const V2 *)&A.y[2 * (long)q];
+                y0[kk] = v.x;
+                y1[kk] = v.y;
+            }
         }
     }
+    __builtin_amdgcn_sched_barrier(0);
+    // metadata of task k+6, columns of task k+4, values of task k+3
+    M[(U + 2) & 3] = meta[task_slice<FWD>(sa, sb, wave, k + 6, nt)];
+    load_cols<T, FWD>(C[U], A, M[U], lane);
+    load_task<T, FWD>(B[(U + 3) & 3], A, M[(U + 3) & 3], lane);
+    __builtin_amdgcn_sched_barrier(0);
+    // t = a - sum_e B_e y_e over this lane's entries; the pair then adds
+    int h = lane & 1;
+    T t0 = h == 0 ? cur.a : (T)0, t1 = h == 0 ? (T)0 : cur.a;
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-        q.L[i] = q.L[i + 1];
-        q.s[i] = q.s[i + 1];
+    for (int kk = 0; kk < MAXK; kk++) {
+        T d0 = cur.v[kk][0] * y0[kk] + cur.v[kk][1] * y1[kk];
+        T d1 = cur.v[kk][2] * y0[kk] + cur.v[kk][3] * y1[kk];
+        t0 -= on[kk] ? d0 : (T)0;
+        t1 -= on[kk] ? d1 : (T)0;
     }
-    q.L[4] = L5;
-    q.s[4] = s5;
+    if (cur.w > MAXK) {
+        // rows with more than 2 MAXK entries (well rows): the rest from memory
+        const int *cols = FWD ? A.lcol : A.ucol;
+        const T *vals = FWD ? A.lval : A.uval;
+        for (int kk = MAXK; kk < cur.w; kk++) {
+            long idx = (long)cur.b + (long)kk * RAS_SLICE + lane;
+            int q = cols[idx];
+            bool ok = q >= 0 && q < A.mtot;
+            int qs = ok ? q : 0;
+            bool inwin = FWD ? qs >= hi - win : qs < lo + win;
+            V2 gv = *(const V2 *)&A.y[2 * (long)qs];
+            V2 rv = *(const V2 *)&ring[2 * (qs & (R - 1))];
+            T a0 = inwin ? rv.x : gv.x, a1 = inwin ? rv.y : gv.y;
+            T e0 = vals[4 * idx] * a0 + vals[4 * idx + 1] * a1;
+            T e1 = vals[4 * idx + 2] * a0 + vals[4 * idx + 3] * a1;
+            t0 -= ok ? e0 : (T)0;
+            t1 -= ok ? e1 : (T)0;
+        }
+    }
+    t0 += __shfl_xor(t0, 1, 64);
+    t1 += __shfl_xor(t1, 1, 64);
+    T out = FWD ? (h == 0 ? t0 : t1) : cur.d0 * t0 + cur.d1 * t1;
+    int r = lane >> 1;
+    if (r < cur.cn) {
+        long p = (long)cur.st + r;
+        A.y[2 * p + h] = out;
+        ring[2 * (p & (R - 1)) + h] = out;
+    }
 }
 
 // One triangular sweep of a subdomain: forward (L, unit diagonal) or
-// backward (U, then the inverse diagonal block).  A wavefront walks its
-// tasks (slices) in level order; every wavefront passes one workgroup
-// barrier per level, in the same sequence, wherever it has work.
+// backward (U, then the inverse diagonal block).  Every wavefront passes one
+// workgroup barrier per level, in the same sequence, wherever it has work.
 template <class T, bool FWD>
-__device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *soff, int nlev,
-                                          int wave, int lane) {
-    const int dir = FWD ? 1 : -1;
-    const int4 *meta = FWD ? A.mL : A.mU;
-    Tasks q;
-    int L = FWD ? -1 : nlev, sl = -1;
-#pragma unroll
-    for (int i = 0; i < 5; i++) {
-        next_task(soff, nlev, dir, wave, L, sl);
-        q.L[i] = L = __builtin_amdgcn_readfirstlane(L);
-        q.s[i] = sl = __builtin_amdgcn_readfirstlane(sl);
-    }
-    Row<T> b0, b1, b2, b3;
-    fetch_row<T, FWD>(b0, A, load_meta(meta, q.s[0]), q.s[0] >= 0, lane);
-    fetch_row<T, FWD>(b1, A, load_meta(meta, q.s[1]), q.s[1] >= 0, lane);
-    fetch_row<T, FWD>(b2, A, load_meta(meta, q.s[2]), q.s[2] >= 0, lane);
-    int4 mfill = load_meta(meta, q.s[3]);
+__device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *lp, T *ring, int win,
+                                          int sa, int sb, int nlev, int wave, int lane) {
+    int nsl = sb - sa;
+    int nt = nsl > wave ? (nsl - wave + NCW - 1) / NCW : 0;
     int passed = 0;
-    while (q.s[0] >= 0) {
-        sweep_step<T, FWD>(A, soff, nlev, wave, lane, b0, b3, mfill, q, passed);
-        if (q.s[0] < 0) break;
-        sweep_step<T, FWD>(A, soff, nlev, wave, lane, b1, b0, mfill, q, passed);
-        if (q.s[0] < 0) break;
-        sweep_step<T, FWD>(A, soff, nlev, wave, lane, b2, b1, mfill, q, passed);
-        if (q.s[0] < 0) break;
-        sweep_step<T, FWD>(A, soff, nlev, wave, lane, b3, b2, mfill, q, passed);
+    if (nt > 0) {
+        const int4 *meta = FWD ? A.mL : A.mU;
+        Task<T> B[4];
+        int C[4][MAXK];
+        int4 M[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) M[j] = meta[task_slice<FWD>(sa, sb, wave, j, nt)];
+#pragma unroll
+        for (int j = 0; j < 4; j++) load_cols<T, FWD>(C[j], A, M[j], lane);
+#pragma unroll
+        for (int j = 0; j < 3; j++) load_task<T, FWD>(B[j], A, M[j], lane);
+        M[0] = meta[task_slice<FWD>(sa, sb, wave, 4, nt)];
+        M[1] = meta[task_slice<FWD>(sa, sb, wave, 5, nt)];
+        // nothing is finished before the first two tasks
+        B[0].pf = B[1].pf = FWD ? lp[0] : lp[nlev];
+        for (int k = 0; k < nt; k += 4) {
+            sweep_step<T, FWD, 0>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k, B, C, M, passed);
+            if (k + 1 >= nt) break;
+            sweep_step<T, FWD, 1>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k + 1, B, C, M, passed);
+            if (k + 2 >= nt) break;
+            sweep_step<T, FWD, 2>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k + 2, B, C, M, passed);
+            if (k + 3 >= nt) break;
+            sweep_step<T, FWD, 3>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k + 3, B, C, M, passed);
+        }
     }
     while (passed < nlev) {
         __syncthreads();
@@ -617,23 +657,38 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *soff
 // gathered right-hand side; the result overwrites y in local order.
 template <class T>
 __global__ __launch_bounds__(SWG) void k_ras_sweep(SweepArgs<T> A) {
-    __shared__ int soff[MAXLEV + 1];
+    constexpr int R = RingSize<T>::rows;
+    __shared__ int lp[MAXLEV + 1];
+    __shared__ int maxw;
+    __shared__ __attribute__((aligned(16))) T ring[2 * R];
     int s = blockIdx.x;
     int nlev = A.nlev[s], base = A.lbase[s];
-    for (int L = threadIdx.x; L <= nlev; L += SWG) soff[L] = A.soff[base + L];
+    if (threadIdx.x == 0) maxw = 0;
+    for (int i = threadIdx.x; i < 2 * R; i += SWG) ring[i] = (T)0;
     __syncthreads();
+    int mw = 0;
+    for (int L = threadIdx.x; L <= nlev; L += SWG) {
+        lp[L] = A.lptr[base + L];
+        if (L < nlev) mw = max(mw, A.lptr[base + L + 1] - A.lptr[base + L]);
+    }
+    atomicMax(&maxw, mw);
+    int sa = A.soff[base], sb = A.soff[base + nlev];
+    __syncthreads();
+    int win = maxw <= R ? R : 0;
     int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
-    sweep_dir<T, true>(A, soff, nlev, wave, lane);
-    sweep_dir<T, false>(A, soff, nlev, wave, lane);
+    sweep_dir<T, true>(A, lp, ring, win, sa, sb, nlev, wave, lane);
+    sweep_dir<T, false>(A, lp, ring, win, sa, sb, nlev, wave, lane);
 }
 
 __global__ void k_slice_meta(int nslice, const int *st, const int *cn, const int *wl,
-                             const int *bl, const int *wu, const int *bu, int4 *mL, int4 *mU) {
+                             const int *bl, const int *wu, const int *bu, const int *perm,
+                             const int *lev, int4 *mL, int4 *mU) {
     int sl = blockIdx.x * blockDim.x + threadIdx.x;
     if (sl >= nslice) return;
-    mL[sl] = make_int4(st[sl], cn[sl], (wl[sl] + 1) / 2, bl[sl]);
-    mU[sl] = make_int4(st[sl], cn[sl], (wu[sl] + 1) / 2, bu[sl]);
+    int L = lev[perm[st[sl]]];
+    mL[sl] = make_int4(st[sl], cn[sl] | ((wl[sl] + 1) / 2) << 8, bl[sl], L);
+    mU[sl] = make_int4(st[sl], cn[sl] | ((wu[sl] + 1) / 2) << 8, bu[sl], L);
 }
 
 // ----------------------------------------------------------------- set-up
@@ -740,8 +795,8 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     R2P_TRY(D.meta_l.ensure(nslice));
     R2P_TRY(D.meta_u.ensure(nslice));
     k_slice_meta<<<r2p_blocks(nslice, BS), BS, 0, s>>>(nslice, D.sl_start.p, D.sl_cnt.p, D.sl_wl.p,
-                                                       D.sl_bl.p, D.sl_wu.p, D.sl_bu.p,
-                                                       D.meta_l.p, D.meta_u.p);
+                                                       D.sl_bl.p, D.sl_wu.p, D.sl_bu.p, D.perm.p,
+                                                       D.lev.p, D.meta_l.p, D.meta_u.p);
     R2P_LAUNCH();
     D.nlent = nle;
     D.nuent = nue;
@@ -828,9 +883,9 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     k_ras_gather<T><<<nb, BS, 0, s>>>(mtot, D.glob.p, r, rl);
     R2P_LAUNCH();
     SweepArgs<T> A;
-    A.lbase = D.sub_lbase.p; A.nlev = D.sub_nlev.p; A.soff = D.soff.p;
+    A.lbase = D.sub_lbase.p; A.nlev = D.sub_nlev.p; A.soff = D.soff.p; A.lptr = D.lptr_dev.p;
     A.mL = D.meta_l.p; A.mU = D.meta_u.p;
-    A.nl = D.nl.p; A.nu = D.nu.p; A.lcol = D.lcol.p; A.ucol = D.ucol.p;
+    A.lcol = D.lcol.p; A.ucol = D.ucol.p;
     A.lval = F.lval.p; A.uval = F.uval.p; A.dinv = F.dinv.p; A.rl = rl; A.y = y;
     A.mtot = mtot;
     k_ras_sweep<T><<<P->rs.ns, SWG, 0, s>>>(A);
