@@ -555,79 +555,90 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
 }
 
 // --------------------------------------------------------------- V-cycle
+// Levels below the finest are CSR.  A group of G lanes takes one row (lanes
+// stride over its entries, ascending within a lane, then a fixed butterfly),
+// so a wavefront reads the entries of 64 / G consecutive rows contiguously;
+// rows longer than HEAVY get a wavefront each in trailing workgroups.  The
+// iterate every row reads is formed beforehand: the pre-smoothed x = b / d
+// by the restriction that produces b, and the prolonged x + P xc by a pass
+// over the fine rows, so each entry costs one gather.
+constexpr int G = 8;
+
 template <class T>
-struct DownArgs {
-    int n, nbs;                  // rows; workgroups of the one-thread-per-row part
+struct CsrArgs {
+    int n, nbs;                  // rows; workgroups of the G-lanes-per-row part
     const int *heavy;            // rows longer than HEAVY, one wavefront each
     int nheavy;
     const int *rp, *col;
     const T *val, *l1;
     const T *b;                  // right-hand side of this level
-    T *x;                        // pre-smoothed iterate of this level
-    T *r;                        // its residual
+    const T *x;                  // iterate: pre-smoothed (down), prolonged (up)
+    T *xo;                       // down: residual b - A x; up: x + (b - A x) / d
 };
 
-// Pre-smoothing from a zero guess (x = b / d) and the residual r = b - A x.
-// The first nbs workgroups take one row per thread (entries in ascending
-// column order); rows longer than HEAVY are left to the trailing
-// workgroups, one wavefront per row (lanes stride over the entries, then a
-// fixed butterfly), so the sum order is fixed either way.
-template <class T>
-__global__ void k_down(DownArgs<T> A) {
+template <class T, bool UP>
+__global__ __launch_bounds__(256) void k_csr_level(CsrArgs<T> A) {
+    int i, lane0;
+    T acc = (T)0;
     if ((int)blockIdx.x < A.nbs) {
-        int i = blockIdx.x * blockDim.x + threadIdx.x;
-        if (i >= A.n) return;
-        T bi = A.b[i];
-        A.x[i] = bi / A.l1[i];
+        i = xcd_block(blockIdx.x, A.nbs) * (blockDim.x / G) + (int)threadIdx.x / G;
+        lane0 = threadIdx.x % G;
+        if (i >= A.n) return;                 // whole groups leave together
         int z0 = A.rp[i], z1 = A.rp[i + 1];
         if (z1 - z0 > HEAVY) return;
-        T r = bi;
-        for (int z = z0; z < z1; z++) {
-            int j = A.col[z];
-            r -= A.val[z] * (A.b[j] / A.l1[j]);
-        }
-        A.r[i] = r;
+        for (int z = z0 + lane0; z < z1; z += G) acc += A.val[z] * A.x[A.col[z]];
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) acc += __shfl_xor(acc, d, 64);
     } else {
         int w = ((int)blockIdx.x - A.nbs) * (blockDim.x >> 6) + (threadIdx.x >> 6);
         if (w >= A.nheavy) return;
-        int lane = threadIdx.x & 63;
-        int i = A.heavy[w];
-        T acc = (T)0;
-        for (int z = A.rp[i] + lane; z < A.rp[i + 1]; z += 64) {
-            int j = A.col[z];
-            acc += A.val[z] * (A.b[j] / A.l1[j]);
-        }
-        for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
-        if (lane == 0) A.r[i] = A.b[i] - acc;
+        lane0 = threadIdx.x & 63;
+        i = A.heavy[w];
+        for (int z = A.rp[i] + lane0; z < A.rp[i + 1]; z += 64) acc += A.val[z] * A.x[A.col[z]];
+        for (int d = 1; d < 64; d <<= 1) acc += __shfl_xor(acc, d, 64);
     }
+    if (lane0 == 0) A.xo[i] = UP ? A.x[i] + (A.b[i] - acc) / A.l1[i] : A.b[i] - acc;
 }
 
-// Restriction P^T r.  The first nbs workgroups give one thread per coarse
-// row (members summed in ascending order); the trailing workgroups give one
-// wavefront per row with more than BIG members (lanes stride over the
-// members, then a fixed butterfly reduction), so a few very large aggregates
-// do not serialise the launch.  Deterministic either way.
+// Restriction P^T r: a group of G lanes per coarse row (lanes stride over
+// the members, then a fixed butterfly); aggregates with more than BIG
+// members get a wavefront each in trailing workgroups.  When the coarse
+// level is smoothed (xc given), its pre-smoothed iterate b / d is formed here.
 template <class T>
-__global__ void k_restrict(int nc, int nbs, const int *mptr, const int *mem, const int *big,
-                           int nbig, const T *r, T *bc) {
+__global__ __launch_bounds__(256) void k_restrict(int nc, int nbs, const int *mptr, const int *mem,
+                                                  const int *big, int nbig, const T *r, T *bc,
+                                                  const T *l1c, T *xc) {
+    int I, lane0;
+    T acc = (T)0;
     if ((int)blockIdx.x < nbs) {
-        int I = blockIdx.x * blockDim.x + threadIdx.x;
+        I = blockIdx.x * (blockDim.x / G) + (int)threadIdx.x / G;
+        lane0 = threadIdx.x % G;
         if (I >= nc) return;
         int a = mptr[I], b = mptr[I + 1];
         if (b - a > BIG) return;
-        T acc = (T)0;
-        for (int t = a; t < b; t++) acc += r[mem[t]];
-        bc[I] = acc;
+        for (int t = a + lane0; t < b; t += G) acc += r[mem[t]];
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) acc += __shfl_xor(acc, d, 64);
     } else {
         int w = ((int)blockIdx.x - nbs) * (blockDim.x >> 6) + (threadIdx.x >> 6);
         if (w >= nbig) return;
-        int lane = threadIdx.x & 63;
-        int I = big[w];
-        T acc = (T)0;
-        for (int t = mptr[I] + lane; t < mptr[I + 1]; t += 64) acc += r[mem[t]];
-        for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
-        if (lane == 0) bc[I] = acc;
+        lane0 = threadIdx.x & 63;
+        I = big[w];
+        for (int t = mptr[I] + lane0; t < mptr[I + 1]; t += 64) acc += r[mem[t]];
+        for (int d = 1; d < 64; d <<= 1) acc += __shfl_xor(acc, d, 64);
     }
+    if (lane0 == 0) {
+        bc[I] = acc;
+        if (xc) xc[I] = acc / l1c[I];
+    }
+}
+
+// Prolongation of the coarse correction onto a fine level's iterate:
+// x_j += xc[agg_j], one thread per fine row.
+template <class T>
+__global__ void k_prolong(int n, const int *agg, const T *xc, T *x) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) x[j] = x[j] + xc[agg[j]];
 }
 
 // Level 0 in the 7-slot layout: columns are implied by the grid (clamped at
@@ -642,7 +653,7 @@ struct Level0 {
 
 template <class T>
 __global__ void k_down0(Level0<T> A, T *x, T *r) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
     const int order[7] = {5, 3, 1, 0, 2, 4, 6};
     T bi = (T)A.f[(long)A.fstride * i];
@@ -653,14 +664,15 @@ __global__ void k_down0(Level0<T> A, T *x, T *r) {
         int sl = order[oi];
         int j = i + slot_offset(sl, A.nx, A.nxy);
         j = j < 0 ? 0 : (j >= A.n ? A.n - 1 : j);
-        s -= A.v7[(long)sl * A.n + i] * ((T)A.f[(long)A.fstride * j] / A.l1[j]);
+        s -= ld_stream(&A.v7[(long)sl * A.n + i]) * ((T)A.f[(long)A.fstride * j] / A.l1[j]);
     }
     r[i] = s;
 }
 
+// Post-smoothing of level 0 on the prolonged iterate x (= x + P xc).
 template <class T>
-__global__ void k_up0(Level0<T> A, const int *agg, const T *x, const T *xc, double *xo) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_up0(Level0<T> A, const T *x, double *xo) {
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
     const int order[7] = {5, 3, 1, 0, 2, 4, 6};
     T s = (T)A.f[(long)A.fstride * i];
@@ -669,58 +681,9 @@ __global__ void k_up0(Level0<T> A, const int *agg, const T *x, const T *xc, doub
         int sl = order[oi];
         int j = i + slot_offset(sl, A.nx, A.nxy);
         j = j < 0 ? 0 : (j >= A.n ? A.n - 1 : j);
-        s -= A.v7[(long)sl * A.n + i] * (x[j] + xc[agg[j]]);
+        s -= ld_stream(&A.v7[(long)sl * A.n + i]) * x[j];
     }
-    T xi = x[i] + xc[agg[i]];
-    xo[i] = (double)(xi + s / A.l1[i]);
-}
-
-template <class T>
-struct UpArgs {
-    int n, nbs;
-    const int *heavy;
-    int nheavy;
-    const int *rp, *col, *agg;
-    const T *val, *l1;
-    const T *b;
-    const T *x;                  // pre-smoothed iterate
-    const T *xc;                 // coarse correction
-    T *xo;                       // output (this level's result)
-};
-
-// Prolongation of the coarse correction and post-smoothing of one fine row:
-// x' = x + P xc; x'' = x' + (b - A x') / d.  Rows are split between threads
-// and wavefronts as in k_down.
-template <class T>
-__global__ void k_up(UpArgs<T> A) {
-    if ((int)blockIdx.x < A.nbs) {
-        int i = blockIdx.x * blockDim.x + threadIdx.x;
-        if (i >= A.n) return;
-        int z0 = A.rp[i], z1 = A.rp[i + 1];
-        if (z1 - z0 > HEAVY) return;
-        T r = A.b[i];
-        for (int z = z0; z < z1; z++) {
-            int j = A.col[z];
-            r -= A.val[z] * (A.x[j] + A.xc[A.agg[j]]);
-        }
-        T xi = A.x[i] + A.xc[A.agg[i]];
-        A.xo[i] = xi + r / A.l1[i];
-    } else {
-        int w = ((int)blockIdx.x - A.nbs) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-        if (w >= A.nheavy) return;
-        int lane = threadIdx.x & 63;
-        int i = A.heavy[w];
-        T acc = (T)0;
-        for (int z = A.rp[i] + lane; z < A.rp[i + 1]; z += 64) {
-            int j = A.col[z];
-            acc += A.val[z] * (A.x[j] + A.xc[A.agg[j]]);
-        }
-        for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
-        if (lane == 0) {
-            T xi = A.x[i] + A.xc[A.agg[i]];
-            A.xo[i] = xi + (A.b[i] - acc) / A.l1[i];
-        }
-    }
+    xo[i] = (double)(x[i] + s / A.l1[i]);
 }
 
 // Coarsest solve x = A_c^-1 b with the stored inverse (column-major, so a
@@ -771,10 +734,19 @@ static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStrea
     auto vxo = [&](AmgLevel &A) -> T * {
         if constexpr (sizeof(T) == 4) return A.xof.p; else return (T *)A.xo.p;
     };
+    auto csr_args = [&](AmgLevel &A) {
+        CsrArgs<T> a;
+        a.n = A.n; a.nbs = r2p_blocks(A.n, BS / G);
+        a.heavy = A.heavy.p; a.nheavy = A.nheavy;
+        a.rp = A.rp.p; a.col = A.col.p; a.val = vals(A); a.l1 = l1s(A);
+        a.b = vb(A);
+        a.x = nullptr; a.xo = nullptr;
+        return a;
+    };
     if (nl == 1) {
         AmgLevel &C = P->lv[0];
-        k_coarse_solve<T><<<r2p_blocks(C.n, 64), 64 * CS_WAVES, 0, s>>>(C.n, P->cinv.p, vb(C), f,
-                                                                       fstride, vx(C), xp);
+        k_coarse_solve<T><<<r2p_blocks(C.n, 64), 64 * CS_WAVES, 0, s>>>(
+            C.n, P->cinv.p, vb(C), f, fstride, vx(C), xp);
         R2P_LAUNCH();
         return 0;
     }
@@ -792,43 +764,36 @@ static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStrea
         if (l == 0) {
             k_down0<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(Z, vx(A), vxo(A));
         } else {
-            DownArgs<T> D;
-            D.n = A.n; D.nbs = r2p_blocks(A.n, BS);
-            D.heavy = A.heavy.p; D.nheavy = A.nheavy;
-            D.rp = A.rp.p; D.col = A.col.p;
-            D.val = vals(A); D.l1 = l1s(A);
-            D.b = vb(A);
-            D.x = vx(A); D.r = vxo(A);
-            k_down<T><<<D.nbs + r2p_blocks(A.nheavy, BS / 64), BS, 0, s>>>(D);
+            CsrArgs<T> D = csr_args(A);
+            D.x = vx(A); D.xo = vxo(A);
+            k_csr_level<T, false><<<D.nbs + r2p_blocks(A.nheavy, BS / 64), BS, 0, s>>>(D);
         }
         R2P_LAUNCH();
-        int nbs = r2p_blocks(C.n, BS);
+        bool smooth = l + 1 < nl - 1;
+        int nbs = r2p_blocks(C.n, BS / G);
         k_restrict<T><<<nbs + r2p_blocks(A.nbig, BS / 64), BS, 0, s>>>(
-            C.n, nbs, A.mptr.p, A.mem.p, A.big.p, A.nbig, vxo(A), vb(C));
+            C.n, nbs, A.mptr.p, A.mem.p, A.big.p, A.nbig, vxo(A), vb(C),
+            smooth ? l1s(C) : nullptr, smooth ? vx(C) : nullptr);
         R2P_LAUNCH();
     }
     AmgLevel &Cst = P->lv[nl - 1];
-    k_coarse_solve<T><<<r2p_blocks(Cst.n, 64), 64 * CS_WAVES, 0, s>>>(Cst.n, P->cinv.p, vb(Cst),
-                                                                     nullptr, 1, vxo(Cst), nullptr);
+    k_coarse_solve<T><<<r2p_blocks(Cst.n, 64), 64 * CS_WAVES, 0, s>>>(
+        Cst.n, P->cinv.p, vb(Cst), nullptr, 1, vxo(Cst), nullptr);
     R2P_LAUNCH();
-    for (int l = nl - 2; l >= 0; l--) {
+    for (int l = nl - 2; l >= 1; l--) {
         AmgLevel &A = P->lv[l];
         AmgLevel &C = P->lv[l + 1];
-        if (l == 0) {
-            k_up0<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(Z, A.agg.p, vx(A), vxo(C), xp);
-            R2P_LAUNCH();
-            continue;
-        }
-        UpArgs<T> U;
-        U.n = A.n; U.nbs = r2p_blocks(A.n, BS);
-        U.heavy = A.heavy.p; U.nheavy = A.nheavy;
-        U.rp = A.rp.p; U.col = A.col.p; U.agg = A.agg.p; U.val = vals(A); U.l1 = l1s(A);
-        U.b = vb(A);
-        U.x = vx(A); U.xc = vxo(C);
-        U.xo = vxo(A);
-        k_up<T><<<U.nbs + r2p_blocks(A.nheavy, BS / 64), BS, 0, s>>>(U);
+        k_prolong<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, A.agg.p, vxo(C), vx(A));
+        R2P_LAUNCH();
+        CsrArgs<T> U = csr_args(A);
+        U.x = vx(A); U.xo = vxo(A);
+        k_csr_level<T, true><<<U.nbs + r2p_blocks(A.nheavy, BS / 64), BS, 0, s>>>(U);
         R2P_LAUNCH();
     }
+    k_prolong<T><<<r2p_blocks(Z.n, BS), BS, 0, s>>>(Z.n, P->lv[0].agg.p, vxo(P->lv[1]), vx(P->lv[0]));
+    R2P_LAUNCH();
+    k_up0<T><<<r2p_blocks(Z.n, BS), BS, 0, s>>>(Z, vx(P->lv[0]), xp);
+    R2P_LAUNCH();
     return 0;
 }
 

@@ -623,7 +623,7 @@ struct SpmvArgs {
 
 __global__ __launch_bounds__(256) void k_spmv(SpmvArgs A) {
     if ((int)blockIdx.x < A.ncellblk) {
-        int c = blockIdx.x * blockDim.x + threadIdx.x;
+        int c = xcd_block(blockIdx.x, A.ncellblk) * blockDim.x + threadIdx.x;
         if (c >= A.n) return;
         const double2 *xv = (const double2 *)A.x;
         const int order[7] = {5, 3, 1, 0, 2, 4, 6};
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(256) void k_spmv(SpmvArgs A) {
             int sl = order[oi];
             int col = c + slot_offset(sl, A.nx, A.nxy);
             col = col < 0 ? 0 : (col >= A.n ? A.n - 1 : col);
-            double2 P = A.vp[(long)sl * A.n + c], S = A.vs[(long)sl * A.n + c];
+            double2 P = ld_stream2(&A.vp[(long)sl * A.n + c]), S = ld_stream2(&A.vs[(long)sl * A.n + c]);
             double2 xc = xv[col];
             y0 += P.x * xc.x + S.x * xc.y;
             y1 += P.y * xc.x + S.y * xc.y;
@@ -703,7 +703,7 @@ extern "C" int r2p_spmv(r2p_jacobian *J, const double *x, double *y, void *strea
 // the well rows' cell blocks (Eq 35 puts zeros in s_w and p_b).
 __global__ __launch_bounds__(256) void k_pcol_residual(SpmvArgs A) {
     if ((int)blockIdx.x < A.ncellblk) {
-        int c = blockIdx.x * blockDim.x + threadIdx.x;
+        int c = xcd_block(blockIdx.x, A.ncellblk) * blockDim.x + threadIdx.x;
         if (c >= A.n) return;
         const int order[7] = {5, 3, 1, 0, 2, 4, 6};
         double y0 = 0.0, y1 = 0.0;
@@ -712,7 +712,7 @@ __global__ __launch_bounds__(256) void k_pcol_residual(SpmvArgs A) {
             int sl = order[oi];
             int col = c + slot_offset(sl, A.nx, A.nxy);
             col = col < 0 ? 0 : (col >= A.n ? A.n - 1 : col);
-            double2 P = A.vp[(long)sl * A.n + c];
+            double2 P = ld_stream2(&A.vp[(long)sl * A.n + c]);
             double xc = A.x[col];
             y0 += P.x * xc;
             y1 += P.y * xc;

@@ -266,6 +266,27 @@ int r2p_scan_int(const int *in, int *out, int n, int *total_host, DBuf<int> &tmp
 
 inline int r2p_blocks(long n, int bs) { return (int)((n + bs - 1) / bs); }
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD
+// b mod 8), each XCD with its own L2.  This renumbering gives XCD x a
+// contiguous range of the nb logical blocks, so grid neighbours read by a
+// stencil (the x vector at +-nx and +-nx*ny) are found in that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    int q = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
+    return x < rem ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
+}
+
+// Streaming load of a 16-byte pair that is read once per launch: marked
+// non-temporal so it does not displace reused data from the caches.
+__device__ __forceinline__ double2 ld_stream2(const double2 *p) {
+    typedef double v2 __attribute__((ext_vector_type(2)));
+    v2 v = __builtin_nontemporal_load((const v2 *)p);
+    return make_double2(v.x, v.y);
+}
+template <class T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
 // Source of a Jacobian block for the subdomain matrices: >= 0 is a slot block
 // index (slot*n + row) into vp/vs; -(1+q) the cell row's well column cw[q];
 // -(1+nperf+q) the well row's cell block wc[q]; -(1+2*nperf+w) the well

@@ -1,0 +1,130 @@
+"""Parity at the benchmark's own size: the 200x200x50 (2M-cell, 25-well)
+correlated-permeability model, through the same library calls and launch
+configuration the benchmark times.
+
+The oracle builds the same Jacobian (about a second), the same CPR set-up
+(a few seconds) and applies it once per call, so the assembled system, the
+residual, SpMV, AMG V-cycle, RAS and CPR applications are compared in full.
+A whole oracle Newton step at this size takes minutes, so the step is
+checked by properties that hold at any size: the linear solve's true
+relative residual, computed with the oracle's decoupled matrix, and the
+oracle's scaled residual at the device's new state.  Tolerances as in the
+small-case parity tests.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+DT = 0.1
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _h(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    from paper_1701_06254_amd import r2p
+    oracle.build(force=False)
+    r2p.load()
+    w = workloads.make_config(1)
+    mo = oracle.Model(w)
+    x0 = mo.initial_state()
+    # a second state with a rough potential field: seeded, from the generator
+    x1 = workloads.random_state(w, np.random.default_rng(21))
+    return dict(w=w, mo=mo, x0=x0, x1=x1, orc=oracle, dev=r2p)
+
+
+def _systems(big, x):
+    orc, dev, mo, w = big["orc"], big["dev"], big["mo"], big["w"]
+    Jo, Fo = mo.jacobian(x, x, DT)
+    mg = dev.Model(w)
+    J = dev.Jacobian(mg)
+    b = J.assemble(_t(x), _t(x), DT)
+    return Jo, Fo, mg, J, b
+
+
+@pytest.mark.parametrize("state", ["x0", "x1"])
+def test_fullsize_residual_and_spmv(big, state):
+    x = big[state]
+    Jo, Fo, mg, J, b = _systems(big, x)
+    assert np.abs(_h(b) + Fo).max() <= 1e-12 * np.abs(Fo).max()
+    v = np.random.default_rng(3).standard_normal(big["mo"].N)
+    yg = _h(J.spmv(_t(v)))
+    yo = Jo.matvec(v)
+    assert np.abs(yg - yo).max() <= 1e-13 * np.abs(yo).max()
+
+
+@pytest.mark.parametrize("state", ["x0", "x1"])
+def test_fullsize_preconditioner(big, state):
+    """AMG hierarchy structure, one V-cycle, one RAS application and one CPR
+    application on the 2M-cell system, each against the oracle."""
+    orc, dev, mo = big["orc"], big["dev"], big["mo"]
+    x = big[state]
+    Jo, Fo, mg, J, b = _systems(big, x)
+    Ad, bd = orc.decouple(Jo, -Fo, mo.n, orc.DEC_QI)
+    Po = orc.Cpr(Ad, mo, x, orc.cpr_opts())
+    P = dev.Cpr().setup(J, dev.cpr_opts())
+    lo, lg = Po.amg_levels(), P.amg_levels()
+    assert [a["A"].n for a in lo] == [g["n"] for g in lg]
+    assert [len(a["A"].col) for a in lo] == [len(g["col"]) for g in lg]
+    assert np.array_equal(lo[1]["A"].col, lg[1]["col"])
+    rng = np.random.default_rng(5)
+    fp = rng.standard_normal(mo.n)
+    xg, xo = _h(P.amg_vcycle(_t(fp))), Po.amg_vcycle(fp)
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+    r = rng.standard_normal(mo.N)
+    yg, yo = _h(P.ras_apply(_t(r))), Po.ras_apply(r)
+    assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(yo)
+    f = rng.standard_normal(mo.N)
+    f[2 * mo.n + 1::2] = 0.0
+    zg, zo = _h(P.apply(_t(f))), Po.apply(f)
+    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("method", ["fgmres", "bicgstab"])
+def test_fullsize_linear_solve(big, method):
+    """The first Newton system of the benchmark (x0, dt 0.1): the device
+    solution's true residual on the oracle's decoupled system <= 1e-8."""
+    orc, dev, mo = big["orc"], big["dev"], big["mo"]
+    Jo, Fo, mg, J, b = _systems(big, big["x0"])
+    Ad, bd = orc.decouple(Jo, -Fo, mo.n, orc.DEC_QI)
+    P = dev.Cpr().setup(J, dev.cpr_opts())
+    m = dev.KRYLOV_FGMRES if method == "fgmres" else dev.KRYLOV_BICGSTAB
+    y, info = dev.solve(J, P, b, dev.solve_opts(method=m))
+    assert info.status == 0 and info.relres <= 1e-8
+    A = Ad.to_scipy()
+    assert np.linalg.norm(bd - A @ _h(y)) <= 1.000001e-8 * np.linalg.norm(bd)
+    print(f"{method}: {info.iterations} iterations at 2M cells")
+
+
+def test_fullsize_newton_step(big):
+    """One implicit step of the benchmark (dt 0.1 from x0): converged by the
+    oracle's own residual and scaled norm at the device's new state."""
+    dev, mo = big["dev"], big["mo"]
+    x0 = big["x0"]
+    mg = dev.Model(big["w"])
+    x = _t(x0)
+    info = mg.newton_step(x, DT)
+    assert info.status == 0
+    x1 = _h(x)
+    F = mo.residual(x1, x0, DT)
+    nrm = mo.scaled_norm(F, DT)
+    print(f"Newton: {info.newton_its} iterations, oracle scaled residual {nrm:.2e}")
+    assert nrm <= 1.01e-8
+    sw = x1[1:2 * mo.n:2]
+    assert np.all(np.isfinite(x1)) and sw.min() >= -1e-12 and sw.max() <= 1 + 1e-12
