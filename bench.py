@@ -49,9 +49,9 @@ HBM_PEAK_GBS = 8000.0
 # 512 MiB device copy, so FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0.
 # Valid only for the RAS source these were taken on (first 16 hex digits of
 # its SHA-256); any change to it reports traffic as null.
-RAS_TRAFFIC = {"source_sha256": "8fd2385f2f8e6ea2",
-               "fetch_kib": 389734.3 + 116761.8 + 21391.5, "fetch_scale": 2.0,
-               "write_kib": 65657.6 + 52280.6 + 62437.4, "write_scale": 1.0}
+RAS_TRAFFIC = {"source_sha256": "1d6023366684c6a3",
+               "fetch_kib": 375605.5 + 117354.0 + 21394.5, "fetch_scale": 2.0,
+               "write_kib": 65590.5 + 52259.3 + 62432.3, "write_scale": 1.0}
 DT_INIT, DT_MIN = 0.1, 1e-4
 GROW_ITS = 6
 
@@ -105,6 +105,47 @@ def spmv_bytes(model):
     offsets and vector entries."""
     n, nw, nperf = model.n, model.nw, model.nperf
     return 7 * 32 * n + 16 * n + 16 * n + nperf * (32 + 32 + 4) + nw * (32 + 8 + 16 + 16)
+
+
+def vcycle_bytes(P, model, prec_bytes=8):
+    """Algorithmic bytes of one AMG V-cycle on the pressure system.
+
+    Level 0 (7-slot stencil): pre-smoothing reads the pressure entries of
+    the right-hand side (whole 16-byte pairs), d and the 7 coefficients and
+    writes x and r (96 B per cell); post-smoothing reads the same plus x and
+    writes the result (96 B); the prolongation onto level 0 reads the
+    aggregate index and x and writes x (20 B).  CSR level l: per entry the
+    value and column, per row the row pointer, b, x and the output (and d on
+    the way up), both ways; restriction: member list, fine residual, member
+    pointers, b and x of the coarse level; prolongation: aggregate index,
+    x read and written.  Coarsest: the dense inverse and two vectors.
+    Neighbour values re-read within a kernel are not counted."""
+    from paper_1701_06254_amd import r2p
+    L = r2p.load()
+    nlev, n, nnz = C.c_int(), C.c_int(), C.c_int()
+    L.r2p_amg_info(P.h, 0, C.byref(nlev), C.byref(n), C.byref(nnz))
+    sizes = []
+    for l in range(nlev.value):
+        L.r2p_amg_info(P.h, l, C.byref(nlev), C.byref(n), C.byref(nnz))
+        sizes.append((n.value, nnz.value))
+    b = prec_bytes
+    nl = len(sizes)
+    if nl == 1:
+        nc = sizes[0][0]
+        return 8 * nc * nc + 16 * nc
+    n0 = sizes[0][0]
+    total = n0 * (16 + b + 7 * b + 2 * b) + n0 * (16 + 7 * b + 3 * b) + n0 * (4 + 2 * b)
+    for l in range(1, nl):
+        nf, nc = sizes[l - 1][0], sizes[l][0]
+        smooth = l < nl - 1
+        total += nf * (4 + b) + 4 * (nc + 1) + nc * b * (3 if smooth else 1)
+        if smooth:
+            n_l, z_l = sizes[l]
+            row = 4 * (n_l + 1) + 12 * z_l
+            total += row + 3 * b * n_l + row + 4 * b * n_l + n_l * (4 + 2 * b)
+    nc = sizes[-1][0]
+    total += 8 * nc * nc + 2 * b * nc
+    return total
 
 
 def time_on_stream(fn, reps):
@@ -190,9 +231,9 @@ def learned_run(args, model, x0, x64, dts, form, log):
     80x80x50 models of the same family (correlated field, wells 40 cells
     apart, 4,000 STB/d injectors, 4,000 psi producers), each run from its cold
     start by the same step-length controller as the timed run (0.1, 0.1,
-    0.2, 0.4, 0.8 days).  Timed steps then take
-    the network's iterate first and fall back to x^n when Newton does not
-    converge from it."""
+    0.2, 0.4, 0.8 days).  Each timed step evaluates the scaled residual at
+    the network's iterate and at x^n and starts Newton from the smaller (the
+    library's default rule); the two norms are reported per step."""
     import numpy as np
     import torch
     import workloads
@@ -223,13 +264,15 @@ def learned_run(args, model, x0, x64, dts, form, log):
     t_fwd = time_on_stream(lambda: net.forward(feat, shape), 5)
     flop = 2 * 27 * (6 * 32 + 8 * 32 * 32 + 32 * 2) * model.n
     o = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, precision=r2p.FP32),
-                        guess_rule=r2p.GUESS_TRY)
+                        guess_rule=r2p.GUESS_SCALED_INF)
     xl = x0.clone()
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     recs = []
+    guesses = []
     for k, dt in enumerate(dts):
         guess = net.warm_start(model, xl, dt)
+        guesses.append(guess)
         info = model.newton_step(xl, dt, o, x_guess=guess)
         recs.append(dict(dt=dt, status=info.status, newton=info.newton_its,
                          linear=info.linear_its, ms_setup=info.ms_setup,
@@ -241,6 +284,17 @@ def learned_run(args, model, x0, x64, dts, form, log):
             break
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t3) * 1e3 / max(len(recs), 1)
+    # untimed: the scaled residual at x^n and at the network's iterate of
+    # every step (replayed from the same states)
+    norms = []
+    Jr = r2p.Jacobian(model)
+    xr = x0.clone()
+    for k, dt in enumerate(dts[:len(recs)]):
+        xo = xr.clone()
+        n0 = model.residual_norm(Jr.assemble(xr, xo, dt), dt)
+        ng = model.residual_norm(Jr.assemble(guesses[k], xo, dt), dt)
+        norms.append([n0, ng])
+        model.newton_step(xr, dt, o)
     sm = summarise(recs)
     n = model.n
     p64, s64 = x64[0:2 * n:2], x64[1:2 * n:2]
@@ -248,6 +302,8 @@ def learned_run(args, model, x0, x64, dts, form, log):
     return dict(ms_per_step=round(ms, 3), solve_ms=round(sm["solve_ms"], 3),
                 newton_its=sm["solves"], linear_its_per_solve=round(sm["its_per_solve"], 2),
                 guess_taken=int(sum(r["used"] for r in recs)), steps=len(recs),
+                guess_rule="scaled residual: the smaller of x^n and the network's iterate",
+                residual_xn_vs_guess=norms,
                 cnn_forward_ms=round(t_fwd, 3),
                 cnn_tflops=round(flop / (t_fwd * 1e-3) / 1e12, 1),
                 converged=all(r["status"] == 0 for r in recs),
@@ -355,7 +411,7 @@ def main():
 
     # per-kernel timing on the last state's first Newton system
     J = r2p.Jacobian(model)
-    J.assemble(x, x, dt_next)
+    bd = J.assemble(x, x, dt_next)
     P = r2p.Cpr().setup(J, o64.cpr)
     v = torch.randn(model.N, dtype=torch.float64, device="cuda")
     y = torch.empty_like(v)
@@ -367,10 +423,24 @@ def main():
     t_cpr = time_on_stream(lambda: P.apply(v, y), 20)
     rb, m_tot, nblk = ras_bytes(P, model, 8)
     sb = spmv_bytes(model)
+    vb = vcycle_bytes(P, model, 8)
     ras_gbs = rb / (t_ras * 1e-3) / 1e9
     spmv_gbs = sb / (t_spmv * 1e-3) / 1e9
+    vcycle_gbs = vb / (t_amg * 1e-3) / 1e9
     log(f"kernels: spmv {t_spmv * 1e3:.1f} us ({spmv_gbs:.0f} GB/s), ras {t_ras * 1e3:.1f} us "
-        f"({ras_gbs:.0f} GB/s), vcycle {t_amg * 1e3:.1f} us, cpr {t_cpr * 1e3:.1f} us")
+        f"({ras_gbs:.0f} GB/s), vcycle {t_amg * 1e3:.1f} us ({vcycle_gbs:.0f} GB/s), "
+        f"cpr {t_cpr * 1e3:.1f} us")
+    # the same Newton system solved by BiCGSTAB (two CPR applications per iteration)
+    krylov = {}
+    for name, method in (("fgmres", r2p.KRYLOV_FGMRES), ("bicgstab", r2p.KRYLOV_BICGSTAB)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = r2p.solve(J, P, bd, r2p.solve_opts(method=method))
+        torch.cuda.synchronize()
+        krylov[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 3),
+                        "iterations": info.iterations, "relres": info.relres,
+                        "status": info.status}
+    log(f"krylov on the last system: {krylov}")
 
     out = {
         "metric": METRIC, "value": round(s64["solve_ms"], 3), "unit": "ms", "n_gpus": 1,
@@ -390,6 +460,11 @@ def main():
         "kernels_us": {"spmv": round(t_spmv * 1e3, 2), "ras_apply": round(t_ras * 1e3, 2),
                        "amg_vcycle": round(t_amg * 1e3, 2), "cpr_apply": round(t_cpr * 1e3, 2)},
         "spmv_gbs": round(spmv_gbs, 1),
+        "spmv_hbm_frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
+        "vcycle_bytes": vb,
+        "vcycle_gbs": round(vcycle_gbs, 1),
+        "vcycle_hbm_frac": round(vcycle_gbs / HBM_PEAK_GBS, 4),
+        "krylov_last_system": krylov,
         "roofline": {"bound": "hbm", "kernel": "ras_apply (k_ras_gather+k_ras_sweep+k_ras_scatter)",
                      "achieved": round(ras_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ras_gbs / HBM_PEAK_GBS, 4), "traffic": ras_traffic(),

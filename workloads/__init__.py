@@ -73,7 +73,7 @@ def gaussian_field(shape, corr_len, rng, pad=30):
     cov = np.exp(-r2 / corr_len ** 2)
     spec = np.abs(np.fft.rfftn(cov))
     noise = rng.standard_normal(full)
-    field = np.fft.irfftn(np.sqrt(spec) * np.fft.rfftn(noise), s=full)
+    field = np.fft.irfftn(np.sqrt(spec) * np.fft.rfftn(noise), s=full, axes=(0, 1, 2))
     field = field[: shape[0], : shape[1], : shape[2]]
     field = (field - field.mean()) / field.std()
     return field
