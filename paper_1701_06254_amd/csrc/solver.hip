@@ -24,77 +24,96 @@ int r2p_decouple_jacobian(r2p_jacobian *J, int kind, hipStream_t s);
 int r2p_newton_update(r2p_model *m, const double *y, double *x, double ds_max, hipStream_t s);
 
 constexpr int BS = 256;
-constexpr int EPT = 16;                 // elements of w per thread in the multi-dot
-constexpr int TILE = BS * EPT;
 constexpr int MAXV = 65;                // basis vectors + 1 (w.w)
+constexpr int MDOT_BLOCKS = 1024;       // workgroups of the multi-dot (grid-stride over rows)
 
 // ----------------------------------------------------------- multi-dot
-// h[k] = V_k . w (k < nv) and h[nv] = w . w.  Each thread keeps EPT
-// elements of w in registers and streams the basis vectors past them; each
-// workgroup writes one partial per k.  The last workgroup to finish (ticket)
-// adds the partials: L lanes per k, each over a fixed stride of workgroups,
-// then a fixed butterfly, so the result does not depend on scheduling.
+// h[k] = V_k . w (k < nv) and h[nv] = w . w, in two launches.  k_mdot: each
+// thread keeps one accumulator per basis vector (NV >= nv, a multiple of 4,
+// unrolled) and walks rows with a grid stride, two rows per visit, so a
+// visit issues the loads of every vector together; the reductions happen
+// once, at the end: a fixed butterfly per wavefront, a fixed sum over the
+// wavefronts, one partial per workgroup and k (k-major).  k_mdot_sum (one
+// workgroup) adds the partials of every k, each thread over a fixed stride
+// of workgroups, then the same butterfly and wavefront sum, so the result
+// does not depend on scheduling.  (A last-workgroup ticket in one launch
+// would need a device-scope fence in every workgroup, which on this GPU
+// writes back and invalidates the L2.)
+template <int NV>
 __global__ __launch_bounds__(BS) void k_mdot(const double *V, long ld, int nv, const double *w,
-                                             long N, double *part, double *h, unsigned *ticket) {
+                                             long N, double *part) {
     __shared__ double red[BS / 64][MAXV];
-    __shared__ bool last;
-    long base = (long)blockIdx.x * TILE + threadIdx.x;
-    double wv[EPT];
+    double acc[NV + 1];
 #pragma unroll
-    for (int e = 0; e < EPT; e++) {
-        long i = base + (long)e * BS;
-        wv[e] = i < N ? w[i] : 0.0;
+    for (int k = 0; k <= NV; k++) acc[k] = 0.0;
+    long stride = (long)gridDim.x * 2 * BS;
+    for (long i0 = (long)blockIdx.x * 2 * BS + threadIdx.x; i0 < N; i0 += stride) {
+        long i1 = i0 + BS;
+        bool two = i1 < N;
+        double w0 = w[i0], w1 = two ? w[i1] : 0.0;
+        // vectors k >= nv re-read the last one (or w): no branch between the
+        // loads, so they are all in flight together; those sums are dropped
+        const double *vl = nv > 0 ? V + (long)(nv - 1) * ld : w;
+        double a[NV], b[NV];
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            const double *vk = k < nv ? V + (long)k * ld : vl;
+            a[k] = vk[i0];
+            b[k] = two ? vk[i1] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < NV; k++) acc[k] += a[k] * w0 + b[k] * w1;
+        acc[NV] += w0 * w0 + w1 * w1;
     }
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k = 0; k <= nv; k++) {
-        double acc = 0.0;
-        if (k < nv) {
-            const double *vk = V + (long)k * ld;
-            double t[EPT];
+    int nb = gridDim.x;
 #pragma unroll
-            for (int e = 0; e < EPT; e++) {
-                long i = base + (long)e * BS;
-                t[e] = i < N ? vk[i] : 0.0;
-            }
-#pragma unroll
-            for (int e = 0; e < EPT; e++) acc += t[e] * wv[e];
-        } else {
-#pragma unroll
-            for (int e = 0; e < EPT; e++) acc += wv[e] * wv[e];
+    for (int k = 0; k <= NV; k++) {
+        if (k < nv || k == NV) {
+            double v = acc[k];
+            for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+            if (lane == 0) red[wid][k < nv ? k : nv] = v;
         }
-        for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
-        if (lane == 0) red[wid][k] = acc;
     }
     __syncthreads();
     for (int k = threadIdx.x; k <= nv; k += BS) {
-        double s = 0.0;
-        for (int q = 0; q < BS / 64; q++) s += red[q][k];
-        part[(long)blockIdx.x * MAXV + k] = s;
+        double t = 0.0;
+        for (int q = 0; q < BS / 64; q++) t += red[q][k];
+        part[(long)k * nb + blockIdx.x] = t;
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    int nb = gridDim.x;
-    int L = 64;                                   // lanes per k: a power of two
-    while (L > 1 && L * (nv + 1) > BS) L >>= 1;
-    int kpp = BS / L;                             // k values per pass
-    for (int k0 = 0; k0 <= nv; k0 += kpp) {
-        int k = k0 + (int)threadIdx.x / L, j = threadIdx.x & (L - 1);
-        double sum = 0.0;
-        if (k <= nv) {
-#pragma unroll 8
-            for (int b = j; b < nb; b += L) sum += part[(long)b * MAXV + k];
-        }
-        for (int d = L >> 1; d > 0; d >>= 1) sum += __shfl_xor(sum, d, 64);
-        if (j == 0 && k <= nv) h[k] = sum;
-    }
-    if (threadIdx.x == 0) *ticket = 0u;
 }
 
-// out = (w - sum_k h[k] V_k) * scale   (out may alias w)
+__global__ __launch_bounds__(BS) void k_mdot_sum(int nv, int nb, const double *part, double *h) {
+    __shared__ double red[BS / 64][MAXV];
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // KT values of k at a time: their loads are in flight together
+    constexpr int KT = 8;
+    for (int k0 = 0; k0 <= nv; k0 += KT) {
+        double sum[KT];
+#pragma unroll
+        for (int u = 0; u < KT; u++) sum[u] = 0.0;
+        for (int b = threadIdx.x; b < nb; b += BS) {
+#pragma unroll
+            for (int u = 0; u < KT; u++) {
+                int k = k0 + u <= nv ? k0 + u : nv;
+                sum[u] += part[(long)k * nb + b];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < KT; u++) {
+            double v = sum[u];
+            for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+            if (lane == 0 && k0 + u <= nv) red[wid][k0 + u] = v;
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k <= nv; k += BS) {
+        double t = 0.0;
+        for (int q = 0; q < BS / 64; q++) t += red[q][k];
+        h[k] = t;
+    }
+}
+
 __global__ __launch_bounds__(BS) void k_mupdate(const double *V, long ld, int nv, const double *h,
                                                 const double *w, long N, double scale,
                                                 double *out) {
@@ -158,7 +177,6 @@ __global__ void k_undecouple(int n, long N, const double4 *dec, const double *rd
 
 struct Krylov {
     DBuf<double> V, Z, part, h, r, bd, w;
-    DBuf<unsigned> ticket;
     HostPinned pin;
     long N = 0;
     int m = 0;
@@ -168,9 +186,22 @@ static Krylov &krylov_for(r2p_cpr *P);
 
 static int mdot(Krylov &K, const double *V, int nv, const double *w, long N, hipStream_t s,
                 double *hhost) {
-    int nb = r2p_blocks(N, TILE);
+    int nb = std::max(1, std::min(MDOT_BLOCKS, r2p_blocks(N, 2 * BS)));
     R2P_TRY(K.part.ensure((size_t)nb * MAXV));
-    k_mdot<<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p, K.h.p, K.ticket.p);
+#define R2P_MDOT(NVB) k_mdot<NVB><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p)
+    if (nv <= 4) R2P_MDOT(4);
+    else if (nv <= 8) R2P_MDOT(8);
+    else if (nv <= 12) R2P_MDOT(12);
+    else if (nv <= 16) R2P_MDOT(16);
+    else if (nv <= 20) R2P_MDOT(20);
+    else if (nv <= 24) R2P_MDOT(24);
+    else if (nv <= 28) R2P_MDOT(28);
+    else if (nv <= 32) R2P_MDOT(32);
+    else if (nv <= 48) R2P_MDOT(48);
+    else R2P_MDOT(64);
+#undef R2P_MDOT
+    R2P_LAUNCH();
+    k_mdot_sum<<<1, BS, 0, s>>>(nv, nb, K.part.p, K.h.p);
     R2P_LAUNCH();
     if (hhost) {
         R2P_HIP(hipMemcpyAsync(K.pin.p, K.h.p, sizeof(double) * (nv + 1), hipMemcpyDeviceToHost, s));
@@ -376,10 +407,6 @@ extern "C" int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y
     R2P_TRY(K.bd.ensure(N));
     R2P_TRY(K.h.ensure(MAXV));
     R2P_TRY(K.pin.ensure(sizeof(double) * MAXV * 2));
-    if (!K.ticket.p) {
-        R2P_TRY(K.ticket.ensure(1));
-        R2P_HIP(hipMemsetAsync(K.ticket.p, 0, sizeof(unsigned), s));
-    }
     R2P_TRY(r2p_decouple_rhs(J, b, K.bd.p, s));
     double hb[MAXV];
     R2P_TRY(mdot(K, nullptr, 0, K.bd.p, N, s, hb));
@@ -613,10 +640,6 @@ extern "C" int r2p_newton_step(r2p_model *m, double *x, double dt, const double 
     Krylov &K = krylov_for(W->P);
     R2P_TRY(K.h.ensure(MAXV));
     R2P_TRY(K.pin.ensure(sizeof(double) * MAXV * 2));
-    if (!K.ticket.p) {
-        R2P_TRY(K.ticket.ensure(1));
-        R2P_HIP(hipMemsetAsync(K.ticket.p, 0, sizeof(unsigned), s));
-    }
     if (x_guess) {
         double ng = 0.0, n0 = 0.0, hb[2];
         int rc = 0;
