@@ -610,10 +610,11 @@ int r2p_decouple_rhs(r2p_jacobian *J, const double *b, double *bd, hipStream_t s
 // --------------------------------------------------------------------- SpMV
 // y = A x, or r = f - A x when f != NULL.  One thread per cell row; blocks
 // summed in ascending column order (-z, -y, -x, self, +x, +y, +z, well).
-// Well rows and the dummy rows are handled by trailing workgroups, one
-// wavefront per well.
+// Well rows and the dummy rows come first, one wavefront per well (lanes
+// over the perforations, then a fixed butterfly), in the first nwblk
+// workgroups (a multiple of 8, so the cell blocks keep their XCD order).
 struct SpmvArgs {
-    int n, nx, nxy, nw, ncellblk;
+    int n, nx, nxy, nw, ncellblk, nwblk;
     const double2 *vp, *vs, *cw, *wc;
     const double *wd;
     const int *cell_perf, *perf_well, *perf_cell, *w_ptr;
@@ -622,8 +623,8 @@ struct SpmvArgs {
 };
 
 __global__ __launch_bounds__(256) void k_spmv(SpmvArgs A) {
-    if ((int)blockIdx.x < A.ncellblk) {
-        int c = xcd_block(blockIdx.x, A.ncellblk) * blockDim.x + threadIdx.x;
+    if ((int)blockIdx.x >= A.nwblk) {
+        int c = xcd_block((int)blockIdx.x - A.nwblk, A.ncellblk) * blockDim.x + threadIdx.x;
         if (c >= A.n) return;
         const double2 *xv = (const double2 *)A.x;
         const int order[7] = {5, 3, 1, 0, 2, 4, 6};
@@ -652,19 +653,18 @@ __global__ __launch_bounds__(256) void k_spmv(SpmvArgs A) {
         ((double2 *)A.y)[c] = make_double2(y0, y1);
     } else {
         int lane = threadIdx.x & 63;
-        int w = ((int)blockIdx.x - A.ncellblk) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        int w = (int)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
         if (w >= A.nw) return;
-        // the row's blocks in ascending column order: perforated cells, then
-        // the well itself; lanes take perforations in that order and the sum
-        // is formed serially by lane 0 to keep the summation order.
-        int q0 = A.w_ptr[w], q1 = A.w_ptr[w + 1];
+        // perforated cells' blocks (lanes stride over them, then a fixed
+        // butterfly), then the well's own block
+        double y0 = 0.0;
+        for (int q = A.w_ptr[w] + lane; q < A.w_ptr[w + 1]; q += 64) {
+            int c = A.perf_cell[q];
+            double2 v = A.wc[q];
+            y0 += v.x * A.x[2 * c] + v.y * A.x[2 * c + 1];
+        }
+        for (int d = 1; d < 64; d <<= 1) y0 += __shfl_xor(y0, d, 64);
         if (lane == 0) {
-            double y0 = 0.0;
-            for (int q = q0; q < q1; q++) {
-                int c = A.perf_cell[q];
-                double2 v = A.wc[q];
-                y0 += v.x * A.x[2 * c] + v.y * A.x[2 * c + 1];
-            }
             long rw = A.n + w;
             y0 += A.wd[w] * A.x[2 * rw] + 0.0 * A.x[2 * rw + 1];
             double y1 = 0.0 * A.x[2 * rw] + 1.0 * A.x[2 * rw + 1];
@@ -687,8 +687,8 @@ int r2p_spmv_impl(r2p_jacobian *J, const double *x, double *y, const double *f, 
     A.cell_perf = J->m->cell_perf.p; A.perf_well = J->m->perf_well.p;
     A.perf_cell = J->m->perf_cell.p; A.w_ptr = J->m->w_ptr.p;
     A.x = x; A.f = f; A.y = y;
-    int wblk = r2p_blocks(P.nw, BS / 64);
-    k_spmv<<<A.ncellblk + wblk, BS, 0, s>>>(A);
+    A.nwblk = (r2p_blocks(P.nw, BS / 64) + 7) & ~7;
+    k_spmv<<<A.nwblk + A.ncellblk, BS, 0, s>>>(A);
     R2P_LAUNCH();
     return 0;
 }
@@ -702,8 +702,8 @@ extern "C" int r2p_spmv(r2p_jacobian *J, const double *x, double *y, void *strea
 // r = f - A (Pi_p xp): only the pressure columns of the cell blocks and of
 // the well rows' cell blocks (Eq 35 puts zeros in s_w and p_b).
 __global__ __launch_bounds__(256) void k_pcol_residual(SpmvArgs A) {
-    if ((int)blockIdx.x < A.ncellblk) {
-        int c = xcd_block(blockIdx.x, A.ncellblk) * blockDim.x + threadIdx.x;
+    if ((int)blockIdx.x >= A.nwblk) {
+        int c = xcd_block((int)blockIdx.x - A.nwblk, A.ncellblk) * blockDim.x + threadIdx.x;
         if (c >= A.n) return;
         const int order[7] = {5, 3, 1, 0, 2, 4, 6};
         double y0 = 0.0, y1 = 0.0;
@@ -720,13 +720,17 @@ __global__ __launch_bounds__(256) void k_pcol_residual(SpmvArgs A) {
         ((double2 *)A.y)[c] = make_double2(A.f[2 * c] - y0, A.f[2 * c + 1] - y1);
     } else {
         int lane = threadIdx.x & 63;
-        int w = ((int)blockIdx.x - A.ncellblk) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-        if (w >= A.nw || lane != 0) return;
+        int w = (int)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        if (w >= A.nw) return;
         double y0 = 0.0;
-        for (int q = A.w_ptr[w]; q < A.w_ptr[w + 1]; q++) y0 += A.wc[q].x * A.x[A.perf_cell[q]];
-        long rw = A.n + w;
-        A.y[2 * rw] = A.f[2 * rw] - y0;
-        A.y[2 * rw + 1] = A.f[2 * rw + 1];
+        for (int q = A.w_ptr[w] + lane; q < A.w_ptr[w + 1]; q += 64)
+            y0 += A.wc[q].x * A.x[A.perf_cell[q]];
+        for (int d = 1; d < 64; d <<= 1) y0 += __shfl_xor(y0, d, 64);
+        if (lane == 0) {
+            long rw = A.n + w;
+            A.y[2 * rw] = A.f[2 * rw] - y0;
+            A.y[2 * rw + 1] = A.f[2 * rw + 1];
+        }
     }
 }
 
@@ -739,8 +743,8 @@ int r2p_pcol_residual(r2p_jacobian *J, const double *f, const double *xp, double
     A.cell_perf = J->m->cell_perf.p; A.perf_well = J->m->perf_well.p;
     A.perf_cell = J->m->perf_cell.p; A.w_ptr = J->m->w_ptr.p;
     A.x = xp; A.f = f; A.y = r;
-    int wblk = r2p_blocks(P.nw, BS / 64);
-    k_pcol_residual<<<A.ncellblk + wblk, BS, 0, s>>>(A);
+    A.nwblk = (r2p_blocks(P.nw, BS / 64) + 7) & ~7;
+    k_pcol_residual<<<A.nwblk + A.ncellblk, BS, 0, s>>>(A);
     R2P_LAUNCH();
     return 0;
 }

@@ -369,13 +369,18 @@ __global__ void k_cast(long n, const double *a, T *b) {
 }
 
 // ------------------------------------------------------------------ solve
+// Restriction of r to the overlapped subdomains, into local (level) order:
+// one thread per local row in natural order, so that the reads of r are
+// contiguous along the tiles' rows; each row's pair lands at its position.
 template <class T>
-__global__ void k_ras_gather(int mtot, const int *glob, const double *r, T *rl) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= mtot) return;
-    long g = glob[p];
-    rl[2 * (long)p] = (T)r[2 * g];
-    rl[2 * (long)p + 1] = (T)r[2 * g + 1];
+__global__ void k_ras_gather(int mtot, const int *glob_nat, const int *pos, const double *r,
+                             T *rl) {
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= mtot) return;
+    long g = glob_nat[l], p = pos[l];
+    const double2 v = ((const double2 *)r)[g];
+    rl[2 * p] = (T)v.x;
+    rl[2 * p + 1] = (T)v.y;
 }
 
 // Restricted scatter: owned rows only; optional Pi_p addend on the pressure
@@ -989,7 +994,7 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     RasDyn &D = P->rd;
     int mtot = P->rs.mtot;
     int nb = r2p_blocks(mtot, BS);
-    k_ras_gather<T><<<nb, BS, 0, s>>>(mtot, D.glob.p, r, rl);
+    k_ras_gather<T><<<nb, BS, 0, s>>>(mtot, P->rs.glob_nat.p, D.pos.p, r, rl);
     R2P_LAUNCH();
     SweepArgs<T> A;
     A.lbase = D.sub_lbase.p; A.nlev = D.sub_nlev.p; A.soff = D.soff.p; A.lptr = D.lptr_dev.p;
