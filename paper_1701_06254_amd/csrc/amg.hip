@@ -84,32 +84,70 @@ __global__ void k_long_list(int n, const int *ptr, int thr, const int *scan, int
 }
 
 // ------------------------------------------------------------- matching
+// The row scans below give a group of GS lanes to each row: lanes stride over
+// the row's entries (ascending within a lane), then a butterfly combines the
+// lanes.  The reductions are exact (a maximum, or the strongest column with
+// ties to the smaller column, which is what a scan in ascending column order
+// keeps), so the result equals the sequential one bit for bit.
+constexpr int GS = 8;
+
+__device__ __forceinline__ void row_group(int n, int &i, int &g) {
+    i = blockIdx.x * (blockDim.x / GS) + (int)threadIdx.x / GS;
+    g = threadIdx.x % GS;
+    (void)n;
+}
+
+// (s, j) replaced by (s2, j2) when that is stronger, or as strong with a
+// smaller column (j = -1: none).
+__device__ __forceinline__ void take_stronger(double &s, int &j, double s2, int j2) {
+    if (j2 >= 0 && (j < 0 || s2 > s || (s2 == s && j2 < j))) { s = s2; j = j2; }
+}
+
 __global__ void k_strength_thr(int n, const int *rp, const int *col, const double *val,
                                double theta, double *thr, int *match) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    int i, g;
+    row_group(n, i, g);
+    if (i >= n) return;                        // whole groups leave together
     double mx = 0.0;
-    for (int z = rp[i]; z < rp[i + 1]; z++)
+    for (int z = rp[i] + g; z < rp[i + 1]; z += GS)
         if (col[z] != i && -val[z] > mx) mx = -val[z];
-    thr[i] = theta * mx;
-    match[i] = -1;
+    for (int d = 1; d < GS; d <<= 1) mx = fmax(mx, __shfl_xor(mx, d, 64));
+    if (g == 0) {
+        thr[i] = theta * mx;
+        match[i] = -1;
+    }
+}
+
+// Strongest strong neighbour j of an unmatched row i with match[j] < 0
+// (propose) or >= 0 (join), ties to the smaller column; -1 if none.
+template <bool JOIN>
+__device__ __forceinline__ void strongest(int n, const int *rp, const int *col, const double *val,
+                                          const double *thr, const int *match, int *out) {
+    int i, g;
+    row_group(n, i, g);
+    if (i >= n) return;
+    double best = 0.0;
+    int best_j = -1;
+    if (match[i] < 0) {
+        for (int z = rp[i] + g; z < rp[i + 1]; z += GS) {
+            int j = col[z];
+            double s = -val[z];
+            bool free_j = match[j] < 0;
+            if (j == i || free_j == JOIN || !(s > 0.0) || s < thr[i]) continue;
+            if (s > best) { best = s; best_j = j; }
+        }
+    }
+    for (int d = 1; d < GS; d <<= 1) {
+        double s2 = __shfl_xor(best, d, 64);
+        int j2 = __shfl_xor(best_j, d, 64);
+        take_stronger(best, best_j, s2, j2);
+    }
+    if (g == 0) out[i] = best_j;
 }
 
 __global__ void k_propose(int n, const int *rp, const int *col, const double *val,
                           const double *thr, const int *match, int *prop) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int best_j = -1;
-    if (match[i] < 0) {
-        double best = 0.0;
-        for (int z = rp[i]; z < rp[i + 1]; z++) {
-            int j = col[z];
-            double s = -val[z];
-            if (j == i || match[j] >= 0 || !(s > 0.0) || s < thr[i]) continue;
-            if (s > best) { best = s; best_j = j; }
-        }
-    }
-    prop[i] = best_j;
+    strongest<false>(n, rp, col, val, thr, match, prop);
 }
 
 __global__ void k_accept(int n, const int *prop, int *match) {
@@ -122,19 +160,7 @@ __global__ void k_accept(int n, const int *prop, int *match) {
 // Unmatched rows: strongest strong neighbour that is in a pair (or -1).
 __global__ void k_join(int n, const int *rp, const int *col, const double *val, const double *thr,
                        const int *match, int *jt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int best_j = -1;
-    if (match[i] < 0) {
-        double best = 0.0;
-        for (int z = rp[i]; z < rp[i + 1]; z++) {
-            int j = col[z];
-            double s = -val[z];
-            if (j == i || match[j] < 0 || !(s > 0.0) || s < thr[i]) continue;
-            if (s > best) { best = s; best_j = j; }
-        }
-    }
-    jt[i] = best_j;
+    strongest<true>(n, rp, col, val, thr, match, jt);
 }
 
 __global__ void k_leader_flag(int n, const int *match, const int *jt, int *flag) {
@@ -190,10 +216,11 @@ __global__ void k_member_ptr(int n, int nc, const unsigned *key, int *mptr) {
 // stored column) order and are summed in that order.
 __global__ void k_gal_expand(int n, const int *rp, const int *agg, unsigned *keyI,
                              const int *col, unsigned *keyJ, unsigned *idx) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i, g;
+    row_group(n, i, g);
     if (i >= n) return;
     unsigned I = (unsigned)agg[i];
-    for (int z = rp[i]; z < rp[i + 1]; z++) {
+    for (int z = rp[i] + g; z < rp[i + 1]; z += GS) {
         keyI[z] = I;
         keyJ[z] = (unsigned)agg[col[z]];
         idx[z] = (unsigned)z;
@@ -205,27 +232,27 @@ __global__ void k_gather_u(int m, const unsigned *idx, const unsigned *src, unsi
     if (k < m) dst[k] = src[idx[k]];
 }
 
-__global__ void k_gal_flags(int m, const unsigned *idx, const unsigned *keyI,
-                            const unsigned *keyJz, int *flag) {
+// keyI, keyJ: the terms' coarse rows and columns in sorted order.
+__global__ void k_gal_flags(int m, const unsigned *keyI, const unsigned *keyJ, int *flag) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     bool f = k == 0;
-    if (!f) f = keyI[k] != keyI[k - 1] || keyJz[idx[k]] != keyJz[idx[k - 1]];
+    if (!f) f = keyI[k] != keyI[k - 1] || keyJ[k] != keyJ[k - 1];
     flag[k] = f;
 }
 
 __global__ void k_gal_compress(int m, int nc, const unsigned *idx, const unsigned *keyI,
-                               const unsigned *keyJz, const int *uidx, const double *val,
+                               const unsigned *keyJ, const int *uidx, const double *val,
                                int *rpc, int *colc, double *valc, int nnzc) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) rpc[nc] = nnzc;
     if (k >= m) return;
-    bool first = k == 0 || keyI[k] != keyI[k - 1] || keyJz[idx[k]] != keyJz[idx[k - 1]];
+    bool first = k == 0 || keyI[k] != keyI[k - 1] || keyJ[k] != keyJ[k - 1];
     if (!first) return;
     int u = uidx[k];
-    unsigned I = keyI[k], J = keyJz[idx[k]];
+    unsigned I = keyI[k], J = keyJ[k];
     double s = 0.0;
-    for (int t = k; t < m && keyI[t] == I && keyJz[idx[t]] == J; t++) s += val[idx[t]];
+    for (int t = k; t < m && keyI[t] == I && keyJ[t] == J; t++) s += val[idx[t]];
     colc[u] = (int)J;
     valc[u] = s;
     if (k == 0 || keyI[k - 1] != I) rpc[I] = u;
@@ -363,7 +390,7 @@ static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, c
     R2P_TRY(kt.ensure(nnz));
     R2P_TRY(vt.ensure(nnz));
     R2P_TRY(flag.ensure(nnz + 1));
-    k_gal_expand<<<r2p_blocks(n, BS), BS, 0, s>>>(n, rp, agg, keyI.p, col, keyJz.p, idx.p);
+    k_gal_expand<<<r2p_blocks(n, BS / GS), BS, 0, s>>>(n, rp, agg, keyI.p, col, keyJz.p, idx.p);
     R2P_LAUNCH();
     int bits = r2p_bits_for(nc);
     // stable by coarse column, then stable by coarse row
@@ -373,7 +400,10 @@ static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, c
     k_gather_u<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, idx.p, keyI.p, keyIs.p);
     R2P_LAUNCH();
     R2P_TRY(r2p_sort_pairs(keyIs.p, idx.p, kt.p, vt.p, nnz, bits, hist, P->iscratch, P->pin, s));
-    k_gal_flags<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, idx.p, keyIs.p, keyJz.p, flag.p);
+    // the coarse columns in sorted order, gathered once (kt is free again)
+    k_gather_u<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, idx.p, keyJz.p, kt.p);
+    R2P_LAUNCH();
+    k_gal_flags<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, keyIs.p, kt.p, flag.p);
     R2P_LAUNCH();
     R2P_HIP(hipMemsetAsync(flag.p + nnz, 0, sizeof(int), s));
     int nnz_c = 0;
@@ -381,7 +411,7 @@ static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, c
     R2P_TRY(rpc.ensure(nc + 1));
     R2P_TRY(colc.ensure(nnz_c));
     R2P_TRY(valc.ensure(nnz_c));
-    k_gal_compress<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, nc, idx.p, keyIs.p, keyJz.p, flag.p,
+    k_gal_compress<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, nc, idx.p, keyIs.p, kt.p, flag.p,
                                                      val, rpc.p, colc.p, valc.p, nnz_c);
     R2P_LAUNCH();
     R2P_HIP(hipStreamSynchronize(s));
@@ -400,16 +430,16 @@ static int aggregate_pass(r2p_cpr *P, int n, const int *rp, const int *col, cons
     R2P_TRY(prop.ensure(n));
     R2P_TRY(jt.ensure(n));
     R2P_TRY(flag.ensure(n + 1));
-    int nb = r2p_blocks(n, BS);
-    k_strength_thr<<<nb, BS, 0, s>>>(n, rp, col, val, P->o.theta, thr.p, match.p);
+    int nb = r2p_blocks(n, BS), ng = r2p_blocks(n, BS / GS);
+    k_strength_thr<<<ng, BS, 0, s>>>(n, rp, col, val, P->o.theta, thr.p, match.p);
     R2P_LAUNCH();
     for (int r = 0; r < P->o.match_rounds; r++) {
-        k_propose<<<nb, BS, 0, s>>>(n, rp, col, val, thr.p, match.p, prop.p);
+        k_propose<<<ng, BS, 0, s>>>(n, rp, col, val, thr.p, match.p, prop.p);
         R2P_LAUNCH();
         k_accept<<<nb, BS, 0, s>>>(n, prop.p, match.p);
         R2P_LAUNCH();
     }
-    k_join<<<nb, BS, 0, s>>>(n, rp, col, val, thr.p, match.p, jt.p);
+    k_join<<<ng, BS, 0, s>>>(n, rp, col, val, thr.p, match.p, jt.p);
     R2P_LAUNCH();
     k_leader_flag<<<nb, BS, 0, s>>>(n, match.p, jt.p, flag.p);
     R2P_LAUNCH();

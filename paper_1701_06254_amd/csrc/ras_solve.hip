@@ -75,7 +75,24 @@ __global__ __launch_bounds__(WG) void k_levels(const int *suboff, int n, int ord
             int l = queue[q];
             lev[l] = t;
             int g = glob_nat[l];
-            for (int e = aptr[l]; e < aptr[l + 1]; e++) {
+            int e0 = aptr[l], e1 = aptr[l + 1];
+            // the first AE couplings: their loads, then their decrements, are
+            // all in flight together; a longer row does the rest in turn
+            constexpr int AE = 8;
+            int hh[AE];
+            bool succ[AE];
+#pragma unroll
+            for (int k = 0; k < AE; k++) hh[k] = e0 + k < e1 ? adj[e0 + k] : l;
+#pragma unroll
+            for (int k = 0; k < AE; k++)
+                succ[k] = e0 + k < e1 && before(g, glob_nat[hh[k]], n, order, phi);
+            int old[AE];
+#pragma unroll
+            for (int k = 0; k < AE; k++) old[k] = succ[k] ? atomicSub(&indeg[hh[k]], 1) : 0;
+#pragma unroll
+            for (int k = 0; k < AE; k++)
+                if (succ[k] && old[k] == 1) queue[atomicAdd(&tail, 1)] = hh[k];
+            for (int e = e0 + AE; e < e1; e++) {
                 int h = adj[e];
                 if (before(g, glob_nat[h], n, order, phi) && atomicSub(&indeg[h], 1) == 1)
                     queue[atomicAdd(&tail, 1)] = h;
