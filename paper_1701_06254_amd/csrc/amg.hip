@@ -241,21 +241,30 @@ __global__ void k_gal_flags(int m, const unsigned *keyI, const unsigned *keyJ, i
     flag[k] = f;
 }
 
-__global__ void k_gal_compress(int m, int nc, const unsigned *idx, const unsigned *keyI,
-                               const unsigned *keyJ, const int *uidx, const double *val,
-                               int *rpc, int *colc, double *valc, int nnzc) {
+// The first term of every run of equal (I, J) records where its run starts;
+// the run of output entry u is then [start[u], start[u + 1]).
+__global__ void k_gal_runs(int m, int nc, const unsigned *keyI, const unsigned *keyJ,
+                           const int *uidx, int *start, int *rpc, int nnzc) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0) rpc[nc] = nnzc;
+    if (k == 0) { rpc[nc] = nnzc; start[nnzc] = m; }
     if (k >= m) return;
     bool first = k == 0 || keyI[k] != keyI[k - 1] || keyJ[k] != keyJ[k - 1];
     if (!first) return;
-    int u = uidx[k];
-    unsigned I = keyI[k], J = keyJ[k];
+    start[uidx[k]] = k;
+    if (k == 0 || keyI[k - 1] != keyI[k]) rpc[keyI[k]] = uidx[k];
+}
+
+// One thread per coarse entry: its terms summed in sorted order (ascending
+// fine row, then stored column).
+__global__ void k_gal_sum(int nnzc, const int *start, const unsigned *idx, const unsigned *keyJ,
+                          const double *val, int *colc, double *valc) {
+    int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nnzc) return;
+    int a = start[u], b = start[u + 1];
     double s = 0.0;
-    for (int t = k; t < m && keyI[t] == I && keyJ[t] == J; t++) s += val[idx[t]];
-    colc[u] = (int)J;
+    for (int t = a; t < b; t++) s += val[idx[t]];
+    colc[u] = (int)keyJ[a];
     valc[u] = s;
-    if (k == 0 || keyI[k - 1] != I) rpc[I] = u;
 }
 
 __global__ void k_l1(int n, const int *rp, const double *val, double *l1) {
@@ -411,8 +420,13 @@ static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, c
     R2P_TRY(rpc.ensure(nc + 1));
     R2P_TRY(colc.ensure(nnz_c));
     R2P_TRY(valc.ensure(nnz_c));
-    k_gal_compress<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, nc, idx.p, keyIs.p, kt.p, flag.p,
-                                                     val, rpc.p, colc.p, valc.p, nnz_c);
+    DBuf<int> &start = W.i[2];
+    R2P_TRY(start.ensure(nnz_c + 1));
+    k_gal_runs<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, nc, keyIs.p, kt.p, flag.p, start.p, rpc.p,
+                                                 nnz_c);
+    R2P_LAUNCH();
+    k_gal_sum<<<r2p_blocks(nnz_c, BS), BS, 0, s>>>(nnz_c, start.p, idx.p, kt.p, val, colc.p,
+                                                   valc.p);
     R2P_LAUNCH();
     R2P_HIP(hipStreamSynchronize(s));
     *nnzc = nnz_c;
