@@ -148,6 +148,45 @@ def vcycle_bytes(P, model, prec_bytes=8):
     return total
 
 
+def variants_run(model, x, dt, form):
+    """Method variants on one Newton system (state x, step dt), each solved
+    from scratch with FGMRES(30) to 1e-8: the decoupling x reordering
+    ablation of the paper's Table 4 (NONE, PT, ABF, QI, PT-ABF, PT-QI) and
+    the RAS variants (overlap 1 or 2; 2x2, 4x4 or 8x8 subdomains).  Returns
+    iterations, status and set-up / solve ms per variant."""
+    import torch
+    from paper_1701_06254_amd import r2p
+    rows = []
+    cases = [("NONE", r2p.DEC_NONE, r2p.ORDER_NATURAL, 4, 1),
+             ("PT", r2p.DEC_NONE, r2p.ORDER_POTENTIAL, 4, 1),
+             ("ABF", r2p.DEC_ABF, r2p.ORDER_NATURAL, 4, 1),
+             ("QI", r2p.DEC_QI, r2p.ORDER_NATURAL, 4, 1),
+             ("PT-ABF", r2p.DEC_ABF, r2p.ORDER_POTENTIAL, 4, 1),
+             ("PT-QI", r2p.DEC_QI, r2p.ORDER_POTENTIAL, 4, 1),
+             ("PT-QI overlap 2", r2p.DEC_QI, r2p.ORDER_POTENTIAL, 4, 2),
+             ("PT-QI 2x2 subdomains", r2p.DEC_QI, r2p.ORDER_POTENTIAL, 2, 1),
+             ("PT-QI 8x8 subdomains", r2p.DEC_QI, r2p.ORDER_POTENTIAL, 8, 1)]
+    for name, dec, order, pxy, ov in cases:
+        J = r2p.Jacobian(model)
+        b = J.assemble(x, x, dt)
+        opts = r2p.cpr_opts(decouple=dec, order=order, form=form, px=pxy, py=pxy, overlap=ov)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = r2p.Cpr().setup(J, opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = r2p.solve(J, P, b)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        rows.append({"variant": name, "iterations": info.iterations, "status": info.status,
+                     "relres": info.relres, "setup_ms": round((t1 - t0) * 1e3, 2),
+                     "solve_ms": round((t2 - t1) * 1e3, 2)})
+        log(f"variant {name}: {info.iterations} its status {info.status} "
+            f"setup {rows[-1]['setup_ms']} ms solve {rows[-1]['solve_ms']} ms")
+        del P, J
+    return rows
+
+
 def time_on_stream(fn, reps):
     """Mean ms of fn() over reps calls, from HIP events on the current stream
     (the stream every library call is enqueued on)."""
@@ -328,6 +367,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=20)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the method variants on the last system and the EW-forcing replay")
     ap.add_argument("--train-models", type=int, default=16,
                     help="seeded 80x80x50 models of the same family that give training pairs")
     ap.add_argument("--train-iters", type=int, default=1500)
@@ -441,6 +482,26 @@ def main():
                         "iterations": info.iterations, "relres": info.relres,
                         "status": info.status}
     log(f"krylov on the last system: {krylov}")
+    variants = None if args.no_variants else variants_run(model, x, dt_next, form)
+    # inexact Newton with Eisenstat-Walker forcing on the timed steps' lengths
+    ew = None
+    if not args.no_variants:
+        oew = r2p.newton_opts(cpr=r2p.cpr_opts(form=form), forcing=r2p.FORCING_EW)
+        xe = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, recs_ew = run_steps(model, xe, dt, args.steps, oew, dt_max, "fp64+EW", dts=accepted)
+        torch.cuda.synchronize()
+        ms_ew = (time.perf_counter() - t0) * 1e3 / args.steps
+        sew = summarise(recs_ew)
+        p64, s_64 = x[0:2 * model.n:2], x[1:2 * model.n:2]
+        pe, se = xe[0:2 * model.n:2], xe[1:2 * model.n:2]
+        ew = dict(ms_per_step=round(ms_ew, 3), newton_its=sew["solves"],
+                  linear_its=sew["linear_its"], linear_its_per_solve=round(sew["its_per_solve"], 2),
+                  plain_newton_its=s64["solves"], plain_linear_its=s64["linear_its"],
+                  rel_err_p=float(torch.linalg.norm(pe - p64) / torch.linalg.norm(p64)),
+                  rel_err_sw=float(torch.linalg.norm(se - s_64) /
+                                   max(float(torch.linalg.norm(s_64)), 1e-300)))
 
     out = {
         "metric": METRIC, "value": round(s64["solve_ms"], 3), "unit": "ms", "n_gpus": 1,
@@ -465,6 +526,8 @@ def main():
         "vcycle_gbs": round(vcycle_gbs, 1),
         "vcycle_hbm_frac": round(vcycle_gbs / HBM_PEAK_GBS, 4),
         "krylov_last_system": krylov,
+        "variants_last_system": variants,
+        "inexact_newton_ew": ew,
         "roofline": {"bound": "hbm", "kernel": "ras_apply (k_ras_gather+k_ras_sweep+k_ras_scatter)",
                      "achieved": round(ras_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ras_gbs / HBM_PEAK_GBS, 4), "traffic": ras_traffic(),

@@ -254,3 +254,15 @@ int r2p_scan_int(const int *in, int *out, int n, int *total_host, DBuf<int> &tmp
     }
     return 0;
 }
+
+int r2p_cu_count() {
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (!cache[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 0;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}

@@ -268,6 +268,9 @@ int r2p_scan_int(const int *in, int *out, int n, int *total_host, DBuf<int> &tmp
 
 inline int r2p_blocks(long n, int bs) { return (int)((n + bs - 1) / bs); }
 
+// Compute units of the current device (cached per device).
+int r2p_cu_count();
+
 // Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD
 // b mod 8), each XCD with its own L2.  This renumbering gives XCD x a
 // contiguous range of the nb logical blocks, so grid neighbours read by a

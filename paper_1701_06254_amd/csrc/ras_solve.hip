@@ -430,6 +430,7 @@ struct SweepArgs {
     T *y;
     int mtot;                    // local rows over all subdomains: the extent of y
     int ns;                      // subdomains (sweep workgroups)
+    int helpers;                 // prefetch workgroups per subdomain (0 .. HELPERS)
     int *prog;                   // ns * NCW progress stamps, one per sweep wavefront
     unsigned epoch;              // this launch's number (low byte in every stamp)
 };
@@ -699,16 +700,16 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *lp, 
 // it; it stops when every sweep wavefront has stamped STAMP_DONE, or after
 // HELPER_POLLS polls.
 constexpr int HELPER_POLLS = 1 << 16;
-constexpr int HELPERS = 4;              // prefetch workgroups per subdomain
+constexpr int HELPERS = 4;              // prefetch workgroups per subdomain, when all fit
 constexpr int HELPER_LEAD = 5;          // tasks ahead the sweep requests its own data
 constexpr int HELPER_SPAN = 16;         // tasks further ahead prefetched here
 
 // Bytes [b0, b1) of the array at base (256-byte aligned): prefetch workgroup
-// h of HELPERS touches every HELPERS-th group of blockDim lines.
-__device__ __forceinline__ unsigned touch_lines(const void *base, long b0, long b1, int h,
+// h of nh touches every nh-th group of blockDim lines.
+__device__ __forceinline__ unsigned touch_lines(const void *base, long b0, long b1, int h, int nh,
                                                 unsigned acc) {
     const int *w = (const int *)base;
-    long step = (long)blockDim.x * HELPERS;
+    long step = (long)blockDim.x * nh;
     for (long l = (b0 >> 7) + (long)h * blockDim.x + threadIdx.x; l <= ((b1 - 1) >> 7); l += step)
         acc ^= (unsigned)w[l * 32];
     return acc;
@@ -758,12 +759,14 @@ __device__ void ras_helper(const SweepArgs<T> &A, int s, int h, unsigned *sink) 
         int4 m0 = meta[lo], m1 = meta[hi - 1];
         long e0 = m0.z, e1 = (long)m1.z + (long)(m1.y >> 8) * RAS_SLICE;
         long p0 = m0.x, p1 = (long)m1.x + (m1.y & 255);
-        acc = touch_lines(meta, 16L * lo, 16L * hi, h, acc);
-        acc = touch_lines(d == 0 ? A.lcol : A.ucol, 4 * e0, 4 * e1, h, acc);
-        acc = touch_lines(d == 0 ? A.lval : A.uval, 4 * sizeof(T) * e0, 4 * sizeof(T) * e1, h, acc);
+        int nh = A.helpers;
+        acc = touch_lines(meta, 16L * lo, 16L * hi, h, nh, acc);
+        acc = touch_lines(d == 0 ? A.lcol : A.ucol, 4 * e0, 4 * e1, h, nh, acc);
+        acc = touch_lines(d == 0 ? A.lval : A.uval, 4 * sizeof(T) * e0, 4 * sizeof(T) * e1, h, nh,
+                          acc);
         acc = touch_lines(d == 0 ? (const T *)A.rl : (const T *)A.y, 2 * sizeof(T) * p0,
-                          2 * sizeof(T) * p1, h, acc);
-        if (d == 1) acc = touch_lines(A.dinv, 4 * sizeof(T) * p0, 4 * sizeof(T) * p1, h, acc);
+                          2 * sizeof(T) * p1, h, nh, acc);
+        if (d == 1) acc = touch_lines(A.dinv, 4 * sizeof(T) * p0, 4 * sizeof(T) * p1, h, nh, acc);
     }
     // keep the loads: an impossible value is the only one ever stored
     if (acc == 0x9e3779b9u && threadIdx.x == 0) sink[s] = acc;
@@ -772,8 +775,9 @@ __device__ void ras_helper(const SweepArgs<T> &A, int s, int h, unsigned *sink) 
 // Forward then backward substitution of one subdomain per workgroup on the
 // gathered right-hand side; the result overwrites y in local order.  With
 // nsp = ns rounded up to 8, the grid holds the ns sweep workgroups, padding
-// up to nsp, and HELPERS groups of nsp prefetch workgroups: workgroup b runs
-// on XCD b mod 8, so prefetch workgroup nsp (1 + h) + s of subdomain s shares
+// up to nsp, and A.helpers groups of nsp prefetch workgroups (none unless
+// all of them fit on the device at once, one per CU): workgroup b runs on
+// XCD b mod 8, so prefetch workgroup nsp (1 + h) + s of subdomain s shares
 // the sweep's L2.
 template <class T>
 __global__ __launch_bounds__(SWG) void k_ras_sweep(SweepArgs<T> A) {
@@ -1023,7 +1027,9 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     A.ns = ns;
     A.prog = D.prog.p;
     A.epoch = ++D.epoch;
-    k_ras_sweep<T><<<((ns + 7) & ~7) * (1 + HELPERS), SWG, 0, s>>>(A);
+    int nsp = (ns + 7) & ~7;
+    A.helpers = (1 + HELPERS) * nsp <= r2p_cu_count() ? HELPERS : 0;
+    k_ras_sweep<T><<<nsp * (1 + A.helpers), SWG, 0, s>>>(A);
     R2P_LAUNCH();
     k_ras_scatter<T><<<nb, BS, 0, s>>>(mtot, P->J->m->ph.n, D.glob.p, D.owned.p, y, xp,
                                        accumulate, out);
