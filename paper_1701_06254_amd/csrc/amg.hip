@@ -644,10 +644,12 @@ __global__ __launch_bounds__(256) void k_csr_level(CsrArgs<T> A) {
     if (lane0 == 0) A.xo[i] = UP ? A.x[i] + (A.b[i] - acc) / A.l1[i] : A.b[i] - acc;
 }
 
-// Restriction P^T r: a group of G lanes per coarse row (lanes stride over
-// the members, then a fixed butterfly); aggregates with more than BIG
-// members get a wavefront each in trailing workgroups.  When the coarse
-// level is smoothed (xc given), its pre-smoothed iterate b / d is formed here.
+// Restriction P^T r: a group of GR lanes per coarse row (lanes stride over
+// the members, then a fixed butterfly; aggregates average 2-4 members);
+// aggregates with more than BIG members get a wavefront each in trailing
+// workgroups.  When the coarse level is smoothed (xc given), its
+// pre-smoothed iterate b / d is formed here.
+constexpr int GR = 4;
 template <class T>
 __global__ __launch_bounds__(256) void k_restrict(int nc, int nbs, const int *mptr, const int *mem,
                                                   const int *big, int nbig, const T *r, T *bc,
@@ -655,14 +657,14 @@ __global__ __launch_bounds__(256) void k_restrict(int nc, int nbs, const int *mp
     int I, lane0;
     T acc = (T)0;
     if ((int)blockIdx.x < nbs) {
-        I = blockIdx.x * (blockDim.x / G) + (int)threadIdx.x / G;
-        lane0 = threadIdx.x % G;
+        I = blockIdx.x * (blockDim.x / GR) + (int)threadIdx.x / GR;
+        lane0 = threadIdx.x % GR;
         if (I >= nc) return;
         int a = mptr[I], b = mptr[I + 1];
         if (b - a > BIG) return;
-        for (int t = a + lane0; t < b; t += G) acc += r[mem[t]];
+        for (int t = a + lane0; t < b; t += GR) acc += r[mem[t]];
 #pragma unroll
-        for (int d = 1; d < G; d <<= 1) acc += __shfl_xor(acc, d, 64);
+        for (int d = 1; d < GR; d <<= 1) acc += __shfl_xor(acc, d, 64);
     } else {
         int w = ((int)blockIdx.x - nbs) * (blockDim.x >> 6) + (threadIdx.x >> 6);
         if (w >= nbig) return;
@@ -814,7 +816,7 @@ static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStrea
         }
         R2P_LAUNCH();
         bool smooth = l + 1 < nl - 1;
-        int nbs = r2p_blocks(C.n, BS / G);
+        int nbs = r2p_blocks(C.n, BS / GR);
         k_restrict<T><<<nbs + r2p_blocks(A.nbig, BS / 64), BS, 0, s>>>(
             C.n, nbs, A.mptr.p, A.mem.p, A.big.p, A.nbig, vxo(A), vb(C),
             smooth ? l1s(C) : nullptr, smooth ? vx(C) : nullptr);
