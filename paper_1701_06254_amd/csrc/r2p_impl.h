@@ -163,6 +163,7 @@ struct RasDyn {
     DBuf<int> lev;                        // mtot: level of local row (natural)
     DBuf<int> suboff;                     // ns+1: first local row of every subdomain
     DBuf<int> indeg, queue;               // mtot: level computation (set-up only)
+    DBuf<unsigned char> apred;            // nadj: coupling e of row l is a predecessor of l
     DBuf<int> nlnat, nunat;               // mtot: predecessor / successor counts (natural)
     DBuf<int> pos;                        // mtot: position of local row
     DBuf<int> perm;                       // mtot: local row (natural) at position

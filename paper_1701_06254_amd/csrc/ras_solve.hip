@@ -52,19 +52,40 @@ __device__ __forceinline__ bool before(int h, int g, int n, int order, const dou
 // predecessor was in round t-1, so a row's round is 1 + the deepest round of
 // its predecessors (0 for rows without one).  Each row enters the
 // subdomain's queue once; the order inside a round depends on scheduling,
-// the rounds do not.
-__global__ __launch_bounds__(WG) void k_levels(const int *suboff, int n, int order,
-                                               const double *phi, const int *glob_nat,
-                                               const int *aptr, const int *adj, const int *npred,
+// the rounds do not.  The direction of every coupling comes precomputed
+// (apred).  When the subdomain has at most LEV_LDS_ROWS rows and no
+// in-degree above 255, the in-degrees live in LDS as packed bytes (a 32-bit
+// LDS atomic subtracts 1 from one byte; a counter >= 1 never borrows);
+// otherwise in global memory.
+constexpr int LEV_LDS_WORDS = 38912;              // 152 KiB of packed counters
+constexpr int LEV_LDS_ROWS = 4 * LEV_LDS_WORDS;
+__global__ __launch_bounds__(WG) void k_levels(const int *suboff, const int *aptr, const int *adj,
+                                               const unsigned char *apred, const int *npred,
                                                int *indeg, int *queue, int *lev, int *nlev) {
-    __shared__ int tail;
+    __shared__ unsigned cnt[LEV_LDS_WORDS];
+    __shared__ int tail, maxd;
     int sub = blockIdx.x;
     int a = suboff[sub], b = suboff[sub + 1];
-    if (threadIdx.x == 0) tail = a;
+    if (threadIdx.x == 0) { tail = a; maxd = 0; }
     __syncthreads();
+    int md = 0;
+    for (int l = a + (int)threadIdx.x; l < b; l += WG) md = max(md, npred[l]);
+    atomicMax(&maxd, md);
+    __syncthreads();
+    const bool in_lds = b - a <= LEV_LDS_ROWS && maxd <= 255;
+    if (in_lds) {
+        for (int w = threadIdx.x; w < (b - a + 3) / 4; w += WG) {
+            unsigned v = 0;
+            for (int k = 0; k < 4; k++) {
+                int l = a + 4 * w + k;
+                if (l < b) v |= (unsigned)npred[l] << (8 * k);
+            }
+            cnt[w] = v;
+        }
+    }
     for (int l = a + (int)threadIdx.x; l < b; l += WG) {
         int d = npred[l];
-        indeg[l] = d;
+        if (!in_lds) indeg[l] = d;
         if (d == 0) queue[atomicAdd(&tail, 1)] = l;
     }
     __syncthreads();
@@ -74,28 +95,45 @@ __global__ __launch_bounds__(WG) void k_levels(const int *suboff, int n, int ord
         for (int q = qs + (int)threadIdx.x; q < qe; q += WG) {
             int l = queue[q];
             lev[l] = t;
-            int g = glob_nat[l];
             int e0 = aptr[l], e1 = aptr[l + 1];
-            // the first AE couplings: their loads, then their decrements, are
-            // all in flight together; a longer row does the rest in turn
+            // the first AE couplings' loads and decrements are in flight
+            // together; a longer row does the rest in turn
             constexpr int AE = 8;
             int hh[AE];
             bool succ[AE];
 #pragma unroll
-            for (int k = 0; k < AE; k++) hh[k] = e0 + k < e1 ? adj[e0 + k] : l;
+            for (int k = 0; k < AE; k++) {
+                bool in = e0 + k < e1;
+                hh[k] = in ? adj[e0 + k] : l;
+                succ[k] = in && !apred[e0 + k];
+            }
+            int last[AE];
+#pragma unroll
+            for (int k = 0; k < AE; k++) {
+                last[k] = 0;
+                if (succ[k]) {
+                    if (in_lds) {
+                        int r = hh[k] - a, sh = 8 * (r & 3);
+                        last[k] = ((atomicSub(&cnt[r >> 2], 1u << sh) >> sh) & 255u) == 1u;
+                    } else {
+                        last[k] = atomicSub(&indeg[hh[k]], 1) == 1;
+                    }
+                }
+            }
 #pragma unroll
             for (int k = 0; k < AE; k++)
-                succ[k] = e0 + k < e1 && before(g, glob_nat[hh[k]], n, order, phi);
-            int old[AE];
-#pragma unroll
-            for (int k = 0; k < AE; k++) old[k] = succ[k] ? atomicSub(&indeg[hh[k]], 1) : 0;
-#pragma unroll
-            for (int k = 0; k < AE; k++)
-                if (succ[k] && old[k] == 1) queue[atomicAdd(&tail, 1)] = hh[k];
+                if (last[k]) queue[atomicAdd(&tail, 1)] = hh[k];
             for (int e = e0 + AE; e < e1; e++) {
+                if (apred[e]) continue;
                 int h = adj[e];
-                if (before(g, glob_nat[h], n, order, phi) && atomicSub(&indeg[h], 1) == 1)
-                    queue[atomicAdd(&tail, 1)] = h;
+                bool done;
+                if (in_lds) {
+                    int r = h - a, sh = 8 * (r & 3);
+                    done = ((atomicSub(&cnt[r >> 2], 1u << sh) >> sh) & 255u) == 1u;
+                } else {
+                    done = atomicSub(&indeg[h], 1) == 1;
+                }
+                if (done) queue[atomicAdd(&tail, 1)] = h;
             }
         }
         __syncthreads();
@@ -108,11 +146,16 @@ __global__ __launch_bounds__(WG) void k_levels(const int *suboff, int n, int ord
 }
 
 __global__ void k_pred_count(int mtot, int n, int order, const double *phi, const int *glob_nat,
-                             const int *aptr, const int *adj, int *nl, int *nu) {
+                             const int *aptr, const int *adj, unsigned char *apred, int *nl,
+                             int *nu) {
     int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= mtot) return;
     int g = glob_nat[l], a = 0;
-    for (int e = aptr[l]; e < aptr[l + 1]; e++) a += before(glob_nat[adj[e]], g, n, order, phi);
+    for (int e = aptr[l]; e < aptr[l + 1]; e++) {
+        bool p = before(glob_nat[adj[e]], g, n, order, phi);
+        apred[e] = p;
+        a += p;
+    }
     nl[l] = a;
     nu[l] = aptr[l + 1] - aptr[l] - a;
 }
@@ -850,8 +893,9 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     R2P_TRY(P->pin.ensure(1 << 16));
     int nb = r2p_blocks(mtot, BS);
     // 1. levels of the dependency graph
+    R2P_TRY(D.apred.ensure(S.nadj > 0 ? S.nadj : 1));
     k_pred_count<<<nb, BS, 0, s>>>(mtot, ph.n, order, J->phi_o.p, S.glob_nat.p, S.aptr.p, S.adj.p,
-                                   D.nlnat.p, D.nunat.p);
+                                   D.apred.p, D.nlnat.p, D.nunat.p);
     R2P_LAUNCH();
     R2P_TRY(D.suboff.ensure(ns + 1));
     R2P_TRY(D.indeg.ensure(mtot));
@@ -859,8 +903,8 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     R2P_HIP(hipMemcpyAsync(D.suboff.p, S.h_off.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice, s));
     int *dnlev = D.counters.p + 64;
     int *hflag = (int *)P->pin.p;
-    k_levels<<<ns, WG, 0, s>>>(D.suboff.p, ph.n, order, J->phi_o.p, S.glob_nat.p, S.aptr.p,
-                               S.adj.p, D.nlnat.p, D.indeg.p, D.queue.p, D.lev.p, dnlev);
+    k_levels<<<ns, WG, 0, s>>>(D.suboff.p, S.aptr.p, S.adj.p, D.apred.p, D.nlnat.p, D.indeg.p,
+                               D.queue.p, D.lev.p, dnlev);
     R2P_LAUNCH();
     // 2. level segments
     R2P_HIP(hipMemcpyAsync(hflag, dnlev, sizeof(int) * ns, hipMemcpyDeviceToHost, s));
