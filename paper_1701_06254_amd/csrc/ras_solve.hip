@@ -19,9 +19,11 @@
 // requested three and four steps ahead; the y values its rows need that
 // were finished two steps earlier are requested then; the rest were
 // finished in the last few levels and are read from an LDS ring that holds
-// the results of the most recent rows.  The gather of the right-hand side
-// into local order and the restricted scatter of the result run as separate
-// full-device kernels.
+// the results of the most recent rows.  Four more workgroups per subdomain,
+// on the sweep's XCD, read its progress and touch the static data of the
+// slices it will request next, so those requests find them in that XCD's
+// L2.  The gather of the right-hand side into local order and the
+// restricted scatter of the result run as separate full-device kernels.
 //
 // Compiled without floating-point contraction (reproducible block products).
 #include <algorithm>
@@ -33,7 +35,7 @@ constexpr int BS = 256;
 constexpr int WG = 1024;               // threads of a subdomain workgroup
 constexpr int NWAVE = WG / 64;
 constexpr int SWG = 512;               // sweep workgroup: 8 wavefronts, 256 VGPRs each
-constexpr int NCW = SWG / 64;          // sweep: wavefronts sharing the slices of a level
+constexpr int NCW = SWG / 64;          // sweep: wavefronts taking a subdomain's slices in turn
 constexpr int MAXK = 3;                // entries per lane held in registers (two lanes per row)
 constexpr int MAXLEV = 4096;           // levels per subdomain kept in LDS
 
