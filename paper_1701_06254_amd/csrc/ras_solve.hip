@@ -37,6 +37,7 @@ constexpr int NWAVE = WG / 64;
 constexpr int SWG = 512;               // sweep workgroup: 8 wavefronts, 256 VGPRs each
 constexpr int NCW = SWG / 64;          // sweep: wavefronts taking a subdomain's slices in turn
 constexpr int MAXK = 3;                // entries per lane held in registers (two lanes per row)
+constexpr int RAS_PAD = MAXK * RAS_SLICE;   // padding after the entry arrays: every task reads MAXK slot pairs
 constexpr int MAXLEV = 4096;           // levels per subdomain kept in LDS
 
 // True when global row h precedes global row g in the local order.
@@ -535,8 +536,11 @@ template <class T, bool FWD>
 __device__ __forceinline__ void load_cols(int (&c)[MAXK], const SweepArgs<T> &A, int4 m, int lane) {
     int w = __builtin_amdgcn_readfirstlane(m.y) >> 8, b = __builtin_amdgcn_readfirstlane(m.z);
     const int *cols = FWD ? A.lcol : A.ucol;
+    // slot pairs past the slice's own re-read its last pair (lines already
+    // requested); they are masked where used
 #pragma unroll
-    for (int k = 0; k < MAXK; k++) c[k] = k < w ? cols[(long)b + (long)k * RAS_SLICE + lane] : -1;
+    for (int k = 0; k < MAXK; k++)
+        c[k] = cols[(long)b + (long)min(k, max(w - 1, 0)) * RAS_SLICE + lane];
 }
 
 template <class T, bool FWD>
@@ -562,32 +566,30 @@ __device__ __forceinline__ void load_task(Task<T> &R, const SweepArgs<T> &A, int
     const T *vals = FWD ? A.lval : A.uval;
 #pragma unroll
     for (int k = 0; k < MAXK; k++) {
-        if (k < R.w) {
-            V4 v = *(const V4 *)&vals[4 * ((long)R.b + (long)k * RAS_SLICE + lane)];
-            R.v[k][0] = v.x; R.v[k][1] = v.y; R.v[k][2] = v.z; R.v[k][3] = v.w;
-        } else {
-            R.v[k][0] = R.v[k][1] = R.v[k][2] = R.v[k][3] = (T)0;
-        }
+        long e = (long)R.b + (long)min(k, max(R.w - 1, 0)) * RAS_SLICE + lane;
+        V4 v = *(const V4 *)&vals[4 * e];
+        R.v[k][0] = v.x; R.v[k][1] = v.y; R.v[k][2] = v.z; R.v[k][3] = v.w;
     }
 }
 
 // Load the y values of the entries of a task whose rows were finished when
 // the prefetch is issued (forward: before position `bound`, backward: from
-// `bound` on); the task records the bound.
+// `bound` on) and that will not be in the LDS ring when the task runs (the
+// ring window of the task's level); the task records the bound.
 template <class T, bool FWD>
 __device__ __forceinline__ void prefetch_y(Task<T> &R, const int (&c)[MAXK], const T *y, int mtot,
-                                           int bound) {
+                                           int bound, const int *lp, int win) {
     typedef typename Vec2<T>::type V2;
     R.pf = bound;
+    int wl = FWD ? lp[R.L + 1] - win : lp[R.L] + win;
 #pragma unroll
     for (int k = 0; k < MAXK; k++) {
         int q = c[k];
-        bool far = q >= 0 && q < mtot && (FWD ? q < bound : q >= bound);
-        if (far) {
-            V2 v = *(const V2 *)&y[2 * (long)q];
-            R.yf[k][0] = v.x;
-            R.yf[k][1] = v.y;
-        }
+        bool far = k < R.w && q >= 0 && q < mtot &&
+                   (FWD ? q < bound && q < wl : q >= bound && q >= wl);
+        V2 v = *(const V2 *)&y[2 * (long)(far ? q : 0)];
+        R.yf[k][0] = v.x;
+        R.yf[k][1] = v.y;
     }
 }
 
@@ -620,8 +622,8 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
         passed++;
     }
     int lo = lp[cur.L], hi = lp[cur.L + 1];
-    // entries of task k+2 finished by now
-    prefetch_y<T, FWD>(B[(U + 2) & 3], C[(U + 2) & 3], A.y, A.mtot, FWD ? lo : hi);
+    // entries of task k+2 finished by now and outside its ring window
+    prefetch_y<T, FWD>(B[(U + 2) & 3], C[(U + 2) & 3], A.y, A.mtot, FWD ? lo : hi, lp, win);
     // task k's entries not prefetched: from the ring, else from y
     T y0[MAXK], y1[MAXK];
     bool on[MAXK];
@@ -629,26 +631,27 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
 #pragma unroll
     for (int kk = 0; kk < MAXK; kk++) {
         int q = C[U][kk];
-        on[kk] = q >= 0 && q < A.mtot;
-        bool pre = FWD ? q < cur.pf : q >= cur.pf;
+        on[kk] = kk < cur.w && q >= 0 && q < A.mtot;
+        bool inwin = FWD ? q >= hi - win : q < lo + win;
+        bool pre = (FWD ? q < cur.pf : q >= cur.pf) && !inwin;
         V2 rv = *(const V2 *)&ring[2 * (q & (R - 1))];
         y0[kk] = pre ? cur.yf[kk][0] : rv.x;
         y1[kk] = pre ? cur.yf[kk][1] : rv.y;
-        bool inwin = FWD ? q >= hi - win : q < lo + win;
         slow |= on[kk] && !pre && !inwin;
     }
     if (__builtin_amdgcn_read_exec() & __ballot(slow)) {
 #pragma unroll
         for (int kk = 0; kk < MAXK; kk++) {
             int q = C[U][kk];
-            bool pre = FWD ? q < cur.pf : q >= cur.pf;
             bool inwin = FWD ? q >= hi - win : q < lo + win;
+            bool pre = (FWD ? q < cur.pf : q >= cur.pf) && !inwin;
             if (on[kk] && !pre && !inwin) {
                 V2 v = *(const V2 *)&A.y[2 * (long)q];
                 y0[kk] = v.x;
                 y1[kk] = v.y;
             }
         }
+        __builtin_amdgcn_s_waitcnt(0);      // nothing of this rare path stays in flight
     }
     __builtin_amdgcn_sched_barrier(0);
     // metadata of task k+6, columns of task k+4, values of task k+3
@@ -684,16 +687,19 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
             t0 -= ok ? e0 : (T)0;
             t1 -= ok ? e1 : (T)0;
         }
+        __builtin_amdgcn_s_waitcnt(0);
     }
     t0 += __shfl_xor(t0, 1, 64);
     t1 += __shfl_xor(t1, 1, 64);
     T out = FWD ? (h == 0 ? t0 : t1) : cur.d0 * t0 + cur.d1 * t1;
+    // lanes past the slice's end store its last row again, with that row's
+    // value, so the store needs no branch
     int r = lane >> 1;
-    if (r < cur.cn) {
-        long p = (long)cur.st + r;
-        A.y[2 * p + h] = out;
-        ring[2 * (p & (R - 1)) + h] = out;
-    }
+    int rr = r < cur.cn ? r : cur.cn - 1;
+    out = __shfl(out, 2 * rr + h, 64);
+    long p = (long)cur.st + rr;
+    A.y[2 * p + h] = out;
+    ring[2 * (p & (R - 1)) + h] = out;
 }
 
 // One triangular sweep of a subdomain: forward (L, unit diagonal) or
@@ -720,13 +726,18 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *lp, 
         M[1] = meta[task_slice<FWD>(sa, sb, wave, 5, nt)];
         // nothing is finished before the first two tasks
         B[0].pf = B[1].pf = FWD ? lp[0] : lp[nlev];
+        // enter the loop with nothing in flight, so that the wait counts the
+        // compiler derives at its head follow the steady state
+        __builtin_amdgcn_s_waitcnt(0);
+        // Steps past the wavefront's last task repeat it: its data were read
+        // before its first computation stored anything (backward, y is read
+        // as input and overwritten), its level barrier is already passed, and
+        // it stores the same values again.  With no exit inside the unrolled
+        // body the wait counts at every step follow the steady state.
         for (int k = 0; k < nt; k += 4) {
             sweep_step<T, FWD, 0>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k, B, C, M, passed);
-            if (k + 1 >= nt) break;
             sweep_step<T, FWD, 1>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k + 1, B, C, M, passed);
-            if (k + 2 >= nt) break;
             sweep_step<T, FWD, 2>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k + 2, B, C, M, passed);
-            if (k + 3 >= nt) break;
             sweep_step<T, FWD, 3>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k + 3, B, C, M, passed);
         }
     }
@@ -981,26 +992,26 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     R2P_LAUNCH();
     D.nlent = nle;
     D.nuent = nue;
-    // RAS_SLICE entries of padding after each array: an empty last slice is
-    // still read (and ignored) by the sweep
-    R2P_TRY(D.lcol.ensure(nle + RAS_SLICE));
-    R2P_TRY(D.ucol.ensure(nue + RAS_SLICE));
+    // RAS_PAD entries of padding after each array: the sweep reads MAXK slot
+    // pairs of every slice (the ones past its own are ignored)
+    R2P_TRY(D.lcol.ensure(nle + RAS_PAD));
+    R2P_TRY(D.ucol.ensure(nue + RAS_PAD));
     R2P_TRY(D.lsrc.ensure(nle));
     R2P_TRY(D.usrc.ensure(nue));
-    R2P_HIP(hipMemsetAsync(D.lcol.p, 0xff, sizeof(int) * (size_t)(nle + RAS_SLICE), s));
-    R2P_HIP(hipMemsetAsync(D.ucol.p, 0xff, sizeof(int) * (size_t)(nue + RAS_SLICE), s));
+    R2P_HIP(hipMemsetAsync(D.lcol.p, 0xff, sizeof(int) * (size_t)(nle + RAS_PAD), s));
+    R2P_HIP(hipMemsetAsync(D.ucol.p, 0xff, sizeof(int) * (size_t)(nue + RAS_PAD), s));
     k_fill_entries<<<nb, BS, 0, s>>>(mtot, ph.n, order, J->phi_o.p, D.perm.p, S.glob_nat.p,
                                      S.aptr.p, S.adj.p, S.asrc.p, D.pos.p, D.glob.p, D.sl_of.p,
                                      D.sl_start.p, D.sl_bl.p, D.sl_bu.p, D.lcol.p, D.lsrc.p,
                                      D.ucol.p, D.usrc.p);
     R2P_LAUNCH();
     // 5. numeric factorisation in FP64
-    R2P_TRY(D.f64.lval.ensure(4L * (nle + RAS_SLICE)));
-    R2P_TRY(D.f64.uval.ensure(4L * (nue + RAS_SLICE)));
+    R2P_TRY(D.f64.lval.ensure(4L * (nle + RAS_PAD)));
+    R2P_TRY(D.f64.uval.ensure(4L * (nue + RAS_PAD)));
     R2P_TRY(D.f64.dinv.ensure(4L * mtot));
     // padding slots stay zero (they are loaded, never used)
-    R2P_HIP(hipMemsetAsync(D.f64.lval.p, 0, sizeof(double) * 4 * (size_t)(nle + RAS_SLICE), s));
-    R2P_HIP(hipMemsetAsync(D.f64.uval.p, 0, sizeof(double) * 4 * (size_t)(nue + RAS_SLICE), s));
+    R2P_HIP(hipMemsetAsync(D.f64.lval.p, 0, sizeof(double) * 4 * (size_t)(nle + RAS_PAD), s));
+    R2P_HIP(hipMemsetAsync(D.f64.uval.p, 0, sizeof(double) * 4 * (size_t)(nue + RAS_PAD), s));
     R2P_TRY(P->status.ensure(4));
     R2P_HIP(hipMemsetAsync(P->status.p, 0, sizeof(int), s));
     FactArgs F;
@@ -1011,9 +1022,9 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     F.sl_of = D.sl_of.p; F.nl = D.nl.p; F.nu = D.nu.p; F.dsrc = D.dsrc_pos.p;
     F.lcol = D.lcol.p; F.ucol = D.ucol.p; F.lsrc = D.lsrc.p; F.usrc = D.usrc.p;
     F.lval = D.f64.lval.p; F.uval = D.f64.uval.p; F.dinv = D.f64.dinv.p; F.status = P->status.p;
-    R2P_TRY(D.ldiag.ensure(nle + RAS_SLICE));
+    R2P_TRY(D.ldiag.ensure(nle + RAS_PAD));
     R2P_TRY(D.xptr.ensure(mtot + 1));
-    R2P_HIP(hipMemsetAsync(D.ldiag.p, 0xff, sizeof(int) * (size_t)(nle + RAS_SLICE), s));
+    R2P_HIP(hipMemsetAsync(D.ldiag.p, 0xff, sizeof(int) * (size_t)(nle + RAS_PAD), s));
     R2P_HIP(hipMemsetAsync(D.xptr.p + mtot, 0, sizeof(int), s));
     F.ldiag = D.ldiag.p; F.xptr = D.xptr.p; F.xl = nullptr;
     k_bilu_gather<<<nb, BS, 0, s>>>(mtot, F);
@@ -1029,7 +1040,7 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     k_bilu0<<<ns, WG, 0, s>>>(F);
     R2P_LAUNCH();
     if (P->o.precision == R2P_FP32) {
-        long nlp = 4L * (nle + RAS_SLICE), nup = 4L * (nue + RAS_SLICE);
+        long nlp = 4L * (nle + RAS_PAD), nup = 4L * (nue + RAS_PAD);
         R2P_TRY(D.f32.lval.ensure(nlp));
         R2P_TRY(D.f32.uval.ensure(nup));
         R2P_TRY(D.f32.dinv.ensure(4L * mtot));
