@@ -357,12 +357,149 @@ def learned_run(args, model, x0, x64, dts, form, log):
                           "loss_last20": float(np.mean(losses[-20:]))})
 
 
+def large_run(args, w, log):
+    """The 65.5M-cell channelised model: plain FP64 CPR-FGMRES against the
+    FP32 preconditioner plus the learned warm start, on one GPU.
+
+    Per-kernel times (SpMV, RAS apply, V-cycle) are taken first on the first
+    Newton system, then one warm-up step (0.1 day) and `--steps` timed steps
+    of the controller run in FP64; the FP32 + learned form replays the same
+    step lengths from the same state.  The network is trained beforehand
+    (untimed) on increments of seeded 80x80x40 channelised models (4 wells).
+    Device memory in use is reported after each form."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1701_06254_amd import r2p, warmstart
+
+    def used_gib():
+        free, total = torch.cuda.mem_get_info()
+        return round((total - free) / 2 ** 30, 1)
+
+    model = r2p.Model(w)
+    x = model.initial_state()
+    o64 = r2p.newton_opts()
+    o32 = r2p.newton_opts(cpr=r2p.cpr_opts(precision=r2p.FP32), guess_rule=r2p.GUESS_SCALED_INF)
+    J = r2p.Jacobian(model)
+    J.assemble(x, x, DT_INIT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = r2p.Cpr().setup(J, o64.cpr)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    v = torch.randn(model.N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(v)
+    fp = torch.randn(model.n, dtype=torch.float64, device="cuda")
+    xp = torch.empty_like(fp)
+    t_spmv = time_on_stream(lambda: J.spmv(v, y), 10)
+    t_ras = time_on_stream(lambda: P.ras_apply(v, y), 5)
+    t_amg = time_on_stream(lambda: P.amg_vcycle(fp, xp), 5)
+    rb, m_tot, nblk = ras_bytes(P, model, 8)
+    sb, vb = spmv_bytes(model), vcycle_bytes(P, model, 8)
+    levels = [g["n"] for g in P.amg_levels()]
+    kern = {"spmv_us": round(t_spmv * 1e3, 1), "spmv_gbs": round(sb / (t_spmv * 1e-3) / 1e9, 1),
+            "ras_apply_us": round(t_ras * 1e3, 1),
+            "ras_gbs": round(rb / (t_ras * 1e-3) / 1e9, 1),
+            "vcycle_us": round(t_amg * 1e3, 1), "vcycle_gbs": round(vb / (t_amg * 1e-3) / 1e9, 1),
+            "cpr_setup_ms": round(setup_ms, 1), "amg_levels": levels,
+            "ras_local_rows": m_tot, "ras_offdiag_blocks": nblk}
+    log(f"large: kernels {kern}")
+    del J, P, v, y, fp, xp
+    torch.cuda.empty_cache()
+
+    dt, _ = run_steps(model, x, DT_INIT, args.warmup, o64, float(w["dt"]), "warmup")
+    x0 = x.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, recs = run_steps(model, x, dt, args.steps, o64, float(w["dt"]), "fp64")
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3 / args.steps
+    mem64 = used_gib()
+    s64 = summarise(recs)
+    accepted = [r["dt"] for r in recs if r["status"] == 0]
+
+    t1 = time.perf_counter()
+    pairs = []
+    for seed in range(2001, 2001 + args.train_models):
+        wt = workloads.make_channels(nx=80, ny=80, nz=40, seed=seed, n_channels=4,
+                                     well_pattern=2)
+        mt = r2p.Model(wt)
+        xs = mt.initial_state()
+        warmstart.collect_pairs(mt, xs, [0.1, 0.1, 0.2, 0.4, 0.8], o64, pairs)
+        del mt
+    net = r2p.Cnn(blocks=4)
+    net.set_params(warmstart.init_params(np.random.default_rng(7)))
+    losses = warmstart.train(net, pairs, (40, 80, 80), args.train_iters, batch=2, lr=1e-3,
+                             seed=3, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    del pairs
+    torch.cuda.empty_cache()
+
+    xl = x0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recsl = []
+    for k, dtk in enumerate(accepted):
+        guess = net.warm_start(model, xl, dtk)
+        info = model.newton_step(xl, dtk, o32, x_guess=guess)
+        del guess
+        recsl.append(dict(dt=dtk, status=info.status, newton=info.newton_its,
+                          linear=info.linear_its, ms_setup=info.ms_setup, ms_solve=info.ms_solve,
+                          ms_assemble=info.ms_assemble, ms_total=info.ms_total,
+                          used=info.used_guess))
+        log(f"fp32+learned step {k}: dt {dtk:.4g} d status {info.status} newton "
+            f"{info.newton_its} linear {info.linear_its} guess {info.used_guess} "
+            f"total {info.ms_total:.0f} ms")
+        if info.status != 0:
+            break
+    torch.cuda.synchronize()
+    msl = (time.perf_counter() - t0) * 1e3 / max(len(recsl), 1)
+    meml = used_gib()
+    sl = summarise(recsl)
+    n = model.n
+    p64, s_64 = x[0:2 * n:2], x[1:2 * n:2]
+    pl, s_l = xl[0:2 * n:2], xl[1:2 * n:2]
+    return {
+        "metric": METRIC, "value": round(s64["solve_ms"], 3), "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms64, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w['name']}: {n} cells, {len(w['wells'])} wells, channelised "
+                               f"permeability; dt from {DT_INIT} d; CPR two-stage, QI + local "
+                               "potential order, RAS 4x4 overlap 1 BILU(0), aggregation AMG "
+                               "V(1,1), FGMRES(30) rtol 1e-8",
+                   "cells": n},
+        "dt_days": accepted,
+        "newton_its_per_step": round(s64["solves"] / args.steps, 2),
+        "linear_its_per_solve": round(s64["its_per_solve"], 2),
+        "setup_ms_per_solve": round(s64["setup_ms"], 3),
+        "device_memory_gib": mem64,
+        "kernels": kern,
+        "fp32_learned": {
+            "ms_per_step": round(msl, 3), "solve_ms": round(sl["solve_ms"], 3),
+            "newton_its": sl["solves"], "linear_its_per_solve": round(sl["its_per_solve"], 2),
+            "guess_taken": int(sum(r["used"] for r in recsl)), "steps": len(recsl),
+            "converged": all(r["status"] == 0 for r in recsl),
+            "device_memory_gib": meml,
+            "rel_err_p": float(torch.linalg.norm(pl - p64) / torch.linalg.norm(p64)),
+            "rel_err_sw": float(torch.linalg.norm(s_l - s_64) /
+                                max(float(torch.linalg.norm(s_64)), 1e-300)),
+            "training": {"models": args.train_models, "adam_steps": args.train_iters,
+                         "seconds": round(train_s, 1),
+                         "loss_first20": float(np.mean(losses[:20])),
+                         "loss_last20": float(np.mean(losses[-20:]))}},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1,
+                    help="1: the 2M-cell model (default); 4: the 65.5M-cell channelised model, "
+                         "FP64 against FP32 + learned start (its own JSON line)")
     ap.add_argument("--form", choices=["two-stage", "fpf"], default="two-stage")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -389,6 +526,9 @@ def main():
     r2p.load()
     w = workloads.make_config(args.config)
     log(f"workload {w['name']}: {w['grid']['n']} cells, {len(w['wells'])} wells")
+    if args.config == 4:
+        print(json.dumps(large_run(args, w, log)), flush=True)
+        return
     model = r2p.Model(w)
     x = model.initial_state()
     form = r2p.CPR_FPF if args.form == "fpf" else r2p.CPR_TWO_STAGE

@@ -600,13 +600,15 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
 
 // --------------------------------------------------------------- V-cycle
 // Levels below the finest are CSR.  A group of G lanes takes one row (lanes
-// stride over its entries, ascending within a lane, then a fixed butterfly),
-// so a wavefront reads the entries of 64 / G consecutive rows contiguously;
-// rows longer than HEAVY get a wavefront each in trailing workgroups.  The
-// iterate every row reads is formed beforehand: the pre-smoothed x = b / d
-// by the restriction that produces b, and the prolonged x + P xc by a pass
-// over the fine rows, so each entry costs one gather.
-constexpr int G = 8;
+// stride over its entries two at a time, both requested before either is
+// used, then a fixed butterfly), so a wavefront reads the entries of 64 / G
+// consecutive rows contiguously; with about 8 entries per row every lane
+// issues its loads at once.  Rows longer than HEAVY get a wavefront each in
+// trailing workgroups, four entries per lane in flight.  The iterate every
+// row reads is formed beforehand: the pre-smoothed x = b / d by the
+// restriction that produces b, and the prolonged x + P xc by a pass over the
+// fine rows, so each entry costs one gather.
+constexpr int G = 4;
 
 template <class T>
 struct CsrArgs {
@@ -630,7 +632,13 @@ __global__ __launch_bounds__(256) void k_csr_level(CsrArgs<T> A) {
         if (i >= A.n) return;                 // whole groups leave together
         int z0 = A.rp[i], z1 = A.rp[i + 1];
         if (z1 - z0 > HEAVY) return;
-        for (int z = z0 + lane0; z < z1; z += G) acc += A.val[z] * A.x[A.col[z]];
+        for (int z = z0 + lane0; z < z1; z += 2 * G) {
+            int zb = z + G < z1 ? z + G : z;
+            int ca = A.col[z], cb = A.col[zb];
+            T va = A.val[z], vb = A.val[zb];
+            T xa = A.x[ca], xb = A.x[cb];
+            acc += va * xa + (z + G < z1 ? vb * xb : (T)0);
+        }
 #pragma unroll
         for (int d = 1; d < G; d <<= 1) acc += __shfl_xor(acc, d, 64);
     } else {
@@ -638,7 +646,17 @@ __global__ __launch_bounds__(256) void k_csr_level(CsrArgs<T> A) {
         if (w >= A.nheavy) return;
         lane0 = threadIdx.x & 63;
         i = A.heavy[w];
-        for (int z = A.rp[i] + lane0; z < A.rp[i + 1]; z += 64) acc += A.val[z] * A.x[A.col[z]];
+        int z0 = A.rp[i], z1 = A.rp[i + 1];
+        for (int z = z0 + lane0; z < z1; z += 256) {
+            T t[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                int zz = z + 64 * u < z1 ? z + 64 * u : z;
+                T v = A.val[zz] * A.x[A.col[zz]];
+                t[u] = z + 64 * u < z1 ? v : (T)0;
+            }
+            acc += (t[0] + t[1]) + (t[2] + t[3]);
+        }
         for (int d = 1; d < 64; d <<= 1) acc += __shfl_xor(acc, d, 64);
     }
     if (lane0 == 0) A.xo[i] = UP ? A.x[i] + (A.b[i] - acc) / A.l1[i] : A.b[i] - acc;
@@ -646,8 +664,9 @@ __global__ __launch_bounds__(256) void k_csr_level(CsrArgs<T> A) {
 
 // Restriction P^T r: a group of GR lanes per coarse row (lanes stride over
 // the members, then a fixed butterfly; aggregates average 2-4 members);
-// aggregates with more than BIG members get a wavefront each in trailing
-// workgroups.  When the coarse level is smoothed (xc given), its
+// aggregates with more than BIG members (up to about a thousand on the
+// coarse levels) get a wavefront each in trailing workgroups, four members
+// per lane in flight.  When the coarse level is smoothed (xc given), its
 // pre-smoothed iterate b / d is formed here.
 constexpr int GR = 4;
 template <class T>
@@ -670,7 +689,16 @@ __global__ __launch_bounds__(256) void k_restrict(int nc, int nbs, const int *mp
         if (w >= nbig) return;
         lane0 = threadIdx.x & 63;
         I = big[w];
-        for (int t = mptr[I] + lane0; t < mptr[I + 1]; t += 64) acc += r[mem[t]];
+        int a = mptr[I], b = mptr[I + 1];
+        for (int t = a + lane0; t < b; t += 256) {
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                T rv = r[mem[t + 64 * u < b ? t + 64 * u : t]];
+                v[u] = t + 64 * u < b ? rv : (T)0;
+            }
+            acc += (v[0] + v[1]) + (v[2] + v[3]);
+        }
         for (int d = 1; d < 64; d <<= 1) acc += __shfl_xor(acc, d, 64);
     }
     if (lane0 == 0) {
