@@ -153,7 +153,7 @@ def variants_run(model, x, dt, form):
     """Method variants on one Newton system (state x, step dt), each solved
     from scratch with FGMRES(30) to 1e-8: the decoupling x reordering
     ablation of the paper's Table 4 (NONE, PT, ABF, QI, PT-ABF, PT-QI) and
-    the RAS variants (overlap 1 or 2; 2x2, 4x4 or 8x8 subdomains).  Returns
+    the RAS variants (overlap 1 or 2; 2x2, 4x4, 8x8 or 16x16 subdomains).  Returns
     iterations, status and set-up / solve ms per variant."""
     import torch
     from paper_1701_06254_amd import r2p
@@ -166,7 +166,8 @@ def variants_run(model, x, dt, form):
              ("PT-QI", r2p.DEC_QI, r2p.ORDER_POTENTIAL, 4, 1),
              ("PT-QI overlap 2", r2p.DEC_QI, r2p.ORDER_POTENTIAL, 4, 2),
              ("PT-QI 2x2 subdomains", r2p.DEC_QI, r2p.ORDER_POTENTIAL, 2, 1),
-             ("PT-QI 8x8 subdomains", r2p.DEC_QI, r2p.ORDER_POTENTIAL, 8, 1)]
+             ("PT-QI 8x8 subdomains", r2p.DEC_QI, r2p.ORDER_POTENTIAL, 8, 1),
+             ("PT-QI 16x16 subdomains", r2p.DEC_QI, r2p.ORDER_POTENTIAL, 16, 1)]
     for name, dec, order, pxy, ov in cases:
         J = r2p.Jacobian(model)
         b = J.assemble(x, x, dt)
@@ -376,10 +377,12 @@ def large_run(args, w, log):
         free, total = torch.cuda.mem_get_info()
         return round((total - free) / 2 ** 30, 1)
 
+    px, py = args.tiles
     model = r2p.Model(w)
     x = model.initial_state()
-    o64 = r2p.newton_opts()
-    o32 = r2p.newton_opts(cpr=r2p.cpr_opts(precision=r2p.FP32), guess_rule=r2p.GUESS_SCALED_INF)
+    o64 = r2p.newton_opts(cpr=r2p.cpr_opts(px=px, py=py))
+    o32 = r2p.newton_opts(cpr=r2p.cpr_opts(px=px, py=py, precision=r2p.FP32),
+                          guess_rule=r2p.GUESS_SCALED_INF)
     J = r2p.Jacobian(model)
     J.assemble(x, x, DT_INIT)
     torch.cuda.synchronize()
@@ -467,9 +470,9 @@ def large_run(args, w, log):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{w['name']}: {n} cells, {len(w['wells'])} wells, channelised "
                                f"permeability; dt from {DT_INIT} d; CPR two-stage, QI + local "
-                               "potential order, RAS 4x4 overlap 1 BILU(0), aggregation AMG "
-                               "V(1,1), FGMRES(30) rtol 1e-8",
-                   "cells": n},
+                               f"potential order, RAS {px}x{py} overlap 1 BILU(0), aggregation "
+                               "AMG V(1,1), FGMRES(30) rtol 1e-8",
+                   "cells": n, "subdomains": px * py},
         "dt_days": accepted,
         "newton_its_per_step": round(s64["solves"] / args.steps, 2),
         "linear_its_per_solve": round(s64["its_per_solve"], 2),
@@ -501,6 +504,9 @@ def main():
                     help="1: the 2M-cell model (default); 4: the 65.5M-cell channelised model, "
                          "FP64 against FP32 + learned start (its own JSON line)")
     ap.add_argument("--form", choices=["two-stage", "fpf"], default="two-stage")
+    ap.add_argument("--tiles", type=lambda v: tuple(int(t) for t in v.split("x")), default=(16, 16),
+                    help="RAS subdomain tiles PXxPY for --config 4 (default 16x16, one subdomain "
+                         "per CU; at most 256 in all)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-its", type=int, default=20)

@@ -91,7 +91,8 @@ typedef struct {
     int decouple;      /* R2P_DEC_*: D^-1 of Eq 29 (Quasi-IMPES or ABF) */
     int order;         /* R2P_ORDER_*: local order of each RAS subdomain (Eq 30-32) */
     int form;          /* R2P_CPR_*: two-stage, or Algorithm 2 (FPF) */
-    int px, py;        /* RAS subdomains: px x py tiles of the x-y plane, full z columns (px*py <= 64) */
+    int px, py;        /* RAS subdomains: px x py tiles of the x-y plane, full z columns (px*py <= 256,
+                          px <= nx, py <= ny; a row may lie in at most 16 overlapped tiles) */
     int overlap;       /* RAS overlap in block-graph layers (>= 0) */
     double theta;      /* AMG strength threshold (0.25) */
     int max_coarse;    /* AMG: stop coarsening at this many rows (<= 2048) */

@@ -244,7 +244,7 @@ extern "C" int r2p_cpr_destroy(r2p_cpr *P) {
 
 static int check_opts(const r2p_cpr_opts *o) {
     if (o->decouple < 0 || o->decouple > 2 || o->order < 0 || o->order > 1 || o->form < 0 ||
-        o->form > 1 || o->px < 1 || o->py < 1 || o->px * o->py > 64 || o->overlap < 0 ||
+        o->form > 1 || o->px < 1 || o->py < 1 || o->px * o->py > 256 || o->overlap < 0 ||
         o->overlap > 8 || !(o->theta >= 0) || o->max_coarse < 1 || o->max_coarse > 2048 ||
         o->max_levels < 1 || o->match_rounds < 1 || o->agg_passes < 1 || o->agg_passes > 4 ||
         o->precision < 0 || o->precision > 1) {

@@ -96,6 +96,27 @@ def test_fullsize_preconditioner(big, state):
     assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
 
 
+def test_fullsize_one_subdomain_per_cu(big):
+    """256 subdomains (16 x 16 tiles of about 12 x 12 x 50 cells), one per
+    CU of the device: one RAS and one CPR application at the cold start
+    against the oracle (1e-10)."""
+    orc, dev, mo = big["orc"], big["dev"], big["mo"]
+    x = big["x0"]
+    Jo, Fo, mg, J, b = _systems(big, x)
+    Ad, bd = orc.decouple(Jo, -Fo, mo.n, orc.DEC_QI)
+    Po = orc.Cpr(Ad, mo, x, orc.cpr_opts(px=16, py=16))
+    P = dev.Cpr().setup(J, dev.cpr_opts(px=16, py=16))
+    assert P.ras_info() == 256
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal(mo.N)
+    yg, yo = _h(P.ras_apply(_t(r))), Po.ras_apply(r)
+    assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(yo)
+    f = rng.standard_normal(mo.N)
+    f[2 * mo.n + 1::2] = 0.0
+    zg, zo = _h(P.apply(_t(f))), Po.apply(f)
+    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
 def test_fullsize_fp32_preconditioner(big):
     """The FP32 form of the preconditioner (factors, hierarchy and vectors in
     FP32, coarsest inverse FP64) on the 2M-cell system: one CPR application

@@ -334,6 +334,31 @@ def test_newton_variants_match_oracle(dev, orc, variant):
     print(f"{variant}: linear iterations GPU {lin_g}, oracle {lin_o}")
 
 
+@pytest.mark.parametrize("tiles", [(16, 16), (5, 10)])
+def test_many_subdomains_match(dev, orc, tiles):
+    """Up to 256 subdomains: on the 20x20x5 model 16 x 16 tiles are one or
+    two columns wide, so with overlap 1 a row lies in up to nine tiles (ten
+    with its well); membership, factors and one RAS and one CPR application
+    against the oracle."""
+    px, py = tiles
+    w = workloads.make_small()
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
+        dev, orc, w, 2, orc.cpr_opts(px=px, py=py), dev.cpr_opts(px=px, py=py))
+    subs = Po.subdomains()
+    assert P.ras_info() == len(subs) == px * py
+    for s in range(0, px * py, 7):
+        sg = P.ras_subdomain(s)
+        assert set(sg["glob"]) == set(subs[s]["glob"])
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(mo.N)
+    yg, yo = _h(P.ras_apply(_t(r))), Po.ras_apply(r)
+    assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(yo)
+    f = rng.standard_normal(mo.N)
+    f[2 * mo.n + 1::2] = 0.0
+    zg, zo = _h(P.apply(_t(f))), Po.apply(f)
+    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
 def test_cpr_apply_overlap2_matches(dev, orc):
     """RAS with overlap 2 (the paper's Table 9 variant): one CPR application."""
     w = workloads.make_small()
