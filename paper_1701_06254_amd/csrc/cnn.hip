@@ -12,10 +12,11 @@
 // with zero weights, so every layer is the same 32 -> 32 kernel.
 //
 // Device design.  A convolution is an implicit GEMM: for each of the 27 taps
-// the wavefront multiplies a 64-voxel x 32-channel tile of shifted inputs by
+// a wavefront multiplies 16-voxel x 32-channel blocks of shifted inputs by
 // the tap's 32 x 32 weight block on the matrix cores
-// (v_mfma_f32_16x16x32_bf16, 4 x 2 tiles), weights staged once per
-// workgroup in LDS, a persistent grid.  The input gradient is the same kernel
+// (v_mfma_f32_16x16x32_bf16); a persistent workgroup per CU stages the
+// weights once and each 2 x 8 x 32 output tile's input with its halo in
+// LDS.  The input gradient is the same kernel
 // on mirrored taps with per-tap transposed weights.  The weight gradient is a
 // GEMM over voxels: each wavefront stages 32-voxel chunks of the output
 // gradient and of the tap-shifted input, transposed, in LDS and accumulates
@@ -86,76 +87,172 @@ struct ConvArgs {
 };
 
 // out[v, o] = epilogue(bias[o] + sum_t sum_i x[v + s off_t, i] w[t, o, i]),
-// s = -1 when flip.  One wavefront computes 64 consecutive voxels.
-__global__ __launch_bounds__(CBS) void k_conv(ConvArgs A) {
+// s = -1 when flip.  A workgroup takes tiles of TZ x TY x TX output voxels of
+// one crop in turn: it stages the tile's input with its one-voxel halo (zero
+// outside the crop) in LDS, next to the 27 weight blocks staged once, so the
+// taps read their shifted inputs from LDS with no bounds tests.  The tile's
+// 16 rows of TX voxels make 32 pieces of 16 voxels; each of the 8 wavefronts owns 4
+// pieces and, per tap, multiplies each piece's 16 x 32 input block by the
+// tap's 32 x 32 weight block on the matrix cores (v_mfma_f32_16x16x32_bf16,
+// two 16-channel halves).  A tile reads 1,360 halo voxels for 512 outputs,
+// so each input voxel is fetched from memory about 2.7 times instead of 27.
+constexpr int TZ = 2, TY = 8, TX = 32;
+constexpr int HZ = TZ + 2, HY = TY + 2, HX = TX + 2, HV = HZ * HY * HX;
+constexpr int CWG = 512;                        // convolution workgroup: 8 wavefronts
+constexpr int PIECES = TZ * TY * TX / 16;       // 16-voxel pieces per tile
+constexpr int MT = PIECES / (CWG / 64);         // pieces per wavefront
+constexpr int HCH = (HV * 4 + CWG - 1) / CWG;   // 16-byte halo chunks per thread
+
+struct TileAt {
+    long cb;            // first voxel of the tile's crop
+    int x0, y0, z0;
+};
+// (32-bit arithmetic: the tile count is checked against 2^31 at launch)
+__device__ __forceinline__ TileAt tile_at(int tile, const Geo &g) {
+    const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
+    int rr = tile;
+    TileAt T;
+    T.x0 = (rr % ntx) * TX;
+    rr /= ntx;
+    T.y0 = (rr % nty) * TY;
+    rr /= nty;
+    T.z0 = (rr % ntz) * TZ;
+    rr /= ntz;
+    T.cb = (long)rr * ((long)g.nx * g.ny * g.nz);
+    return T;
+}
+
+// This thread's chunks of a tile's input with halo (zero outside the crop).
+__device__ __forceinline__ void fetch_halo(uint4 (&h)[HCH], const u16 *x, const TileAt &T,
+                                           const Geo &g) {
+#pragma unroll
+    for (int u = 0; u < HCH; u++) {
+        int c = (int)threadIdx.x + u * CWG;
+        int hv = c >> 2, part = c & 3;
+        int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+        int gx = T.x0 + hx - 1, gy = T.y0 + hy - 1, gz = T.z0 + hz - 1;
+        bool in = c < HV * 4 && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 &&
+                  gz < g.nz;
+        long at = in ? (T.cb + ((long)gz * g.ny + gy) * g.nx + gx) * CH + 8 * part : 0;
+        uint4 v = *reinterpret_cast<const uint4 *>(x + at);
+        h[u] = in ? v : uint4{0u, 0u, 0u, 0u};
+    }
+}
+
+__global__ __launch_bounds__(CWG) void k_conv(ConvArgs A) {
     __shared__ __attribute__((aligned(16))) u16 wl[WLAYER];
-    for (int e = threadIdx.x; e < WLAYER / 8; e += CBS)
+    __shared__ __attribute__((aligned(16))) u16 xl[HV * CH];
+    for (int e = threadIdx.x; e < WLAYER / 8; e += CWG)
         reinterpret_cast<uint4 *>(wl)[e] = reinterpret_cast<const uint4 *>(A.w)[e];
-    __syncthreads();
-    const long V = A.g.V();
+    const Geo g = A.g;
+    const int ntile = g.nb * ((g.nz + TZ - 1) / TZ) * ((g.ny + TY - 1) / TY) *
+                      ((g.nx + TX - 1) / TX);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, kg = lane >> 4;
-    const long ntile = (V + 63) / 64;
-    for (long tile = (long)blockIdx.x * 4 + wave; tile < ntile; tile += (long)gridDim.x * 4) {
-        long v[4];
-        int cx[4], cy[4], cz[4];
-        bool ok[4];
+    // the next tile's input is requested into registers before the current
+    // tile is computed, so its memory latency overlaps the matrix work
+    uint4 hreg[HCH];
+    // bias of this thread's eight epilogue channels
+    const int part = threadIdx.x & 3;
+    float bz[8];
 #pragma unroll
-        for (int m = 0; m < 4; m++) {
-            v[m] = tile * 64 + 16 * m + i;
-            ok[m] = v[m] < V;
-            long r = ok[m] ? v[m] : 0;
-            cx[m] = (int)(r % A.g.nx);
-            r /= A.g.nx;
-            cy[m] = (int)(r % A.g.ny);
-            r /= A.g.ny;
-            cz[m] = (int)(r % A.g.nz);
+    for (int u = 0; u < 8; u++) bz[u] = A.bias ? A.bias[8 * part + u] : 0.f;
+    if ((int)blockIdx.x < ntile) fetch_halo(hreg, A.x, tile_at(blockIdx.x, g), g);
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const TileAt T = tile_at(tile, g);
+        const long cb = T.cb;
+        const int x0 = T.x0, y0 = T.y0, z0 = T.z0;
+        __syncthreads();            // weights staged; the previous tile's reads are done
+#pragma unroll
+        for (int u = 0; u < HCH; u++) {
+            int c = (int)threadIdx.x + u * CWG;
+            if (c < HV * 4) reinterpret_cast<uint4 *>(xl)[c] = hreg[u];
         }
-        f32x4 acc[4][2];
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntile) fetch_halo(hreg, A.x, tile_at(tile + gridDim.x, g), g);
+        f32x4 acc[MT][2];
 #pragma unroll
-        for (int m = 0; m < 4; m++)
-            for (int n = 0; n < 2; n++) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < MT; j++) acc[j][0] = acc[j][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // every piece is computed (pieces past the crop's edge read zeros and
+        // are not stored), so a tap is straight-line code: its ten LDS reads
+        // are issued ahead of its sixteen matrix instructions
+#pragma unroll 3
         for (int t = 0; t < TAPS; t++) {
             int dz, dy, dx;
             tap_off(t, dz, dy, dx);
             if (A.flip) { dz = -dz; dy = -dy; dx = -dx; }
-            bf16x8 a[4];
-#pragma unroll
-            for (int m = 0; m < 4; m++) {
-                long nb = ok[m] ? neighbour(v[m], cx[m], cy[m], cz[m], dz, dy, dx, A.g) : -1;
-                uint4 raw = nb >= 0 ? *reinterpret_cast<const uint4 *>(A.x + nb * CH + 8 * kg)
-                                    : uint4{0u, 0u, 0u, 0u};
-                a[m] = __builtin_bit_cast(bf16x8, raw);
-            }
             bf16x8 b[2];
 #pragma unroll
             for (int n = 0; n < 2; n++)
                 b[n] = __builtin_bit_cast(
                     bf16x8, *reinterpret_cast<const uint4 *>(&wl[(t * CH + 16 * n + i) * CH + 8 * kg]));
 #pragma unroll
-            for (int m = 0; m < 4; m++)
-#pragma unroll
-                for (int n = 0; n < 2; n++)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[n], acc[m][n], 0, 0, 0);
+            for (int j = 0; j < MT; j++) {
+                int pc = wave * MT + j, row = pc >> 1;
+                int hv = ((row / TY + 1 + dz) * HY + (row % TY + 1 + dy)) * HX + (pc & 1) * 16 + i + 1 + dx;
+                bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&xl[hv * CH + 8 * kg]));
+                acc[j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[0], acc[j][0], 0, 0, 0);
+                acc[j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[1], acc[j][1], 0, 0, 0);
+            }
         }
-        // result element (row 4 kg + r, column i) of tile (m, n)
+        // The results go through LDS (the halo buffer is free once every
+        // wavefront has finished its taps): element (voxel 4 kg + r of piece
+        // pc, channel 16 n + i) is stored at float [16 pc + 4 kg + r][32];
+        // then each thread takes eight channels of a voxel, so the addend and
+        // mask are read and the result written 16 bytes per lane.
+        float *st = reinterpret_cast<float *>(xl);
+        __syncthreads();
 #pragma unroll
-        for (int m = 0; m < 4; m++)
+        for (int j = 0; j < MT; j++) {
+            int pc = wave * MT + j;
 #pragma unroll
             for (int n = 0; n < 2; n++)
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    long vo = tile * 64 + 16 * m + 4 * kg + r;
-                    if (vo >= V) continue;
-                    int c = 16 * n + i;
-                    float val = acc[m][n][r];
-                    if (A.bias) val += A.bias[c];
-                    if (A.addend) val += from_bf16(A.addend[vo * CH + c]);
-                    if (A.mask && !(from_bf16(A.mask[vo * CH + c]) > 0.f)) val = 0.f;
-                    if (A.relu) val = val > 0.f ? val : 0.f;
-                    if (A.out) A.out[vo * CH + c] = to_bf16(val);
-                    if (A.outf) A.outf[vo * CH + c] = val;
-                }
+                for (int r = 0; r < 4; r++) st[(16 * pc + 4 * kg + r) * CH + 16 * n + i] = acc[j][n][r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PIECES * 16 * 4 / CWG; q++) {
+            int tv = q * (CWG / 4) + (int)(threadIdx.x >> 2);     // voxel of the tile
+            int pc = tv >> 4, row = pc >> 1;
+            int xo = x0 + (pc & 1) * 16 + (tv & 15), yo = y0 + row % TY, zo = z0 + row / TY;
+            if (xo >= g.nx || yo >= g.ny || zo >= g.nz) continue;
+            long vo = cb + ((long)zo * g.ny + yo) * g.nx + xo;
+            float4 r0 = *reinterpret_cast<const float4 *>(&st[tv * CH + 8 * part]);
+            float4 r1 = *reinterpret_cast<const float4 *>(&st[tv * CH + 8 * part + 4]);
+            float val[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+            for (int u = 0; u < 8; u++) val[u] += bz[u];
+            if (A.addend) {
+                uint4 ad = *reinterpret_cast<const uint4 *>(A.addend + vo * CH + 8 * part);
+                const u16 *ah = reinterpret_cast<const u16 *>(&ad);
+#pragma unroll
+                for (int u = 0; u < 8; u++) val[u] += from_bf16(ah[u]);
+            }
+            if (A.mask) {
+                uint4 mk = *reinterpret_cast<const uint4 *>(A.mask + vo * CH + 8 * part);
+                const u16 *mh = reinterpret_cast<const u16 *>(&mk);
+#pragma unroll
+                for (int u = 0; u < 8; u++) val[u] = from_bf16(mh[u]) > 0.f ? val[u] : 0.f;
+            }
+            if (A.relu) {
+#pragma unroll
+                for (int u = 0; u < 8; u++) val[u] = val[u] > 0.f ? val[u] : 0.f;
+            }
+            if (A.out) {
+                uint4 o;
+                u16 *oh = reinterpret_cast<u16 *>(&o);
+#pragma unroll
+                for (int u = 0; u < 8; u++) oh[u] = to_bf16(val[u]);
+                *reinterpret_cast<uint4 *>(A.out + vo * CH + 8 * part) = o;
+            }
+            if (A.outf) {
+                *reinterpret_cast<float4 *>(A.outf + vo * CH + 8 * part) =
+                    make_float4(val[0], val[1], val[2], val[3]);
+                *reinterpret_cast<float4 *>(A.outf + vo * CH + 8 * part + 4) =
+                    make_float4(val[4], val[5], val[6], val[7]);
+            }
+        }
     }
 }
 
@@ -391,11 +488,13 @@ __global__ void k_mask_mul(const u16 *a, const u16 *mask, long n, u16 *out) {
 }
 
 int launch_conv(const ConvArgs &A, hipStream_t s) {
-    long V = A.g.V();
-    long tiles = (V + 63) / 64;
-    int grid = (int)std::min<long>((tiles + 3) / 4, 2048);
+    const Geo &g = A.g;
+    long tiles = (long)g.nb * ((g.nz + TZ - 1) / TZ) * ((g.ny + TY - 1) / TY) * ((g.nx + TX - 1) / TX);
+    if (tiles >= (1L << 31)) { r2p_set_error("convolution grid too large"); return R2P_EINVAL; }
+    // one workgroup per CU (the staged weights and halo take 139 KB of LDS)
+    int grid = (int)std::min<long>(tiles, r2p_cu_count());
     if (grid < 1) grid = 1;
-    k_conv<<<grid, CBS, 0, s>>>(A);
+    k_conv<<<grid, CWG, 0, s>>>(A);
     R2P_LAUNCH();
     return 0;
 }

@@ -35,7 +35,7 @@ def from_bits(t):
     return u.view(np.float32).astype(np.float64)
 
 
-SHAPES = [(2, 3, 5, 7), (2, 8, 16, 20)]
+SHAPES = [(2, 3, 5, 7), (2, 8, 16, 20), (1, 5, 9, 70)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
