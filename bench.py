@@ -45,8 +45,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one RAS apply (k_ras_gather + k_ras_sweep + k_ras_scatter) on
 # the first Newton system of the 2M-cell cold start, from two rocprofv3 --pmc
 # runs of `bench.py --kernels-only` (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch, mean of 5; the sweep's figures include its prefetch workgroups,
-# which belong to the same dispatch).  The same counters read 262,170 / 524,288 KiB for a
+# dispatch, mean of 5).  The same counters read 262,170 / 524,288 KiB for a
 # 512 MiB device copy, so FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0.
 # Valid only for the RAS source these were taken on (first 16 hex digits of
 # its SHA-256); any change to it reports traffic as null.

@@ -175,8 +175,6 @@ struct RasDyn {
     DBuf<int> sl_start, sl_cnt, sl_wl, sl_wu, sl_bl, sl_bu;   // per slice
     DBuf<int> sl_of;                      // mtot: slice of every position
     DBuf<int4> meta_l, meta_u;            // per slice: (start, rows | slot pairs << 8, entry base, level) of L / U
-    DBuf<int> prog;                       // ns * 8: sweep progress stamps read by the prefetch workgroups
-    unsigned epoch = 0;                   // sweep launches so far (stamps carry its low byte)
     DBuf<int> lcol, ucol;                 // entries: column position (-1 padding)
     DBuf<int> lsrc, usrc;                 // entries: block source (set-up only)
     DBuf<int> dsrc_pos;                   // mtot: diagonal block source per position

@@ -19,11 +19,9 @@
 // requested three and four steps ahead; the y values its rows need that
 // were finished two steps earlier are requested then; the rest were
 // finished in the last few levels and are read from an LDS ring that holds
-// the results of the most recent rows.  Four more workgroups per subdomain,
-// on the sweep's XCD, read its progress and touch the static data of the
-// slices it will request next, so those requests find them in that XCD's
-// L2.  The gather of the right-hand side into local order and the
-// restricted scatter of the result run as separate full-device kernels.
+// the results of the most recent rows.  The gather of the right-hand side
+// into local order and the restricted scatter of the result run as separate
+// full-device kernels.
 //
 // Compiled without floating-point contraction (reproducible block products).
 #include <algorithm>
@@ -476,17 +474,7 @@ struct SweepArgs {
     T *y;
     int mtot;                    // local rows over all subdomains: the extent of y
     int ns;                      // subdomains (sweep workgroups)
-    int helpers;                 // prefetch workgroups per subdomain (0 .. HELPERS)
-    int *prog;                   // ns * NCW progress stamps, one per sweep wavefront
-    unsigned epoch;              // this launch's number (low byte in every stamp)
 };
-
-// Progress stamps: (epoch & 255) << 24 | phase, phase = k (forward task k),
-// 2^23 | k (backward task k) or STAMP_DONE.
-constexpr unsigned STAMP_DONE = 0xffffffu;
-__device__ __forceinline__ unsigned stamp(unsigned epoch, unsigned phase) {
-    return (epoch & 255u) << 24 | phase;
-}
 
 // LDS ring of the results of recently finished rows: position p sits in
 // slot p mod RING.  While level L is being computed, a finished position q
@@ -611,11 +599,6 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
     constexpr int R = RingSize<T>::rows;
     const int4 *meta = FWD ? A.mL : A.mU;
     Task<T> &cur = B[U];
-    if (U == 0) {
-        unsigned ph = FWD ? (unsigned)k : (1u << 23) | (unsigned)k;
-        __hip_atomic_store(&A.prog[blockIdx.x * NCW + wave], (int)stamp(A.epoch, ph),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     int rank = FWD ? cur.L : nlev - 1 - cur.L;
     while (passed < rank) {
         __syncthreads();
@@ -747,107 +730,14 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *lp, 
     }
 }
 
-// Prefetch workgroup of subdomain s, on the XCD of its sweep workgroup: it
-// reads the sweep's progress stamps and touches one word of every 128-byte
-// line of the static data (metadata, columns, factor blocks, right-hand side
-// or forward result, inverse diagonal blocks) of the slices the sweep will
-// request next, so that those requests find the lines in that XCD's L2.  It
-// changes no data the sweep reads, so the sweep's results do not depend on
-// it; it stops when every sweep wavefront has stamped STAMP_DONE, or after
-// HELPER_POLLS polls.
-constexpr int HELPER_POLLS = 1 << 16;
-constexpr int HELPERS = 4;              // prefetch workgroups per subdomain, when all fit
-constexpr int HELPER_LEAD = 5;          // tasks ahead the sweep requests its own data
-constexpr int HELPER_SPAN = 16;         // tasks further ahead prefetched here
-
-// Bytes [b0, b1) of the array at base (256-byte aligned): prefetch workgroup
-// h of nh touches every nh-th group of blockDim lines.
-__device__ __forceinline__ unsigned touch_lines(const void *base, long b0, long b1, int h, int nh,
-                                                unsigned acc) {
-    const int *w = (const int *)base;
-    long step = (long)blockDim.x * nh;
-    for (long l = (b0 >> 7) + (long)h * blockDim.x + threadIdx.x; l <= ((b1 - 1) >> 7); l += step)
-        acc ^= (unsigned)w[l * 32];
-    return acc;
-}
-
-template <class T>
-__device__ void ras_helper(const SweepArgs<T> &A, int s, int h, unsigned *sink) {
-    int nlev = A.nlev[s], base = A.lbase[s];
-    int sa = A.soff[base], sb = A.soff[base + nlev];
-    int nsl = sb - sa;
-    if (nsl <= 0) return;
-    unsigned ep = A.epoch & 255u, acc = 0;
-    int pf[2] = {0, 0};                 // slices already prefetched, per direction (in its order)
-    for (int it = 0; it < HELPER_POLLS; it++) {
-        int kmax[2] = {-1, -1};
-        int ndone = 0, nseen = 0;
-        for (int w = 0; w < NCW; w++) {
-            unsigned v = (unsigned)__hip_atomic_load(&A.prog[s * NCW + w], __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-            if ((v >> 24) != ep) continue;
-            nseen++;
-            unsigned ph = v & STAMP_DONE;
-            if (ph == STAMP_DONE) { ndone++; continue; }
-            int d = (int)(ph >> 23);
-            kmax[d] = max(kmax[d], (int)(ph & 0x7fffffu));
-        }
-        if (ndone == NCW) break;
-        // direction and window: backward once a wavefront is in it, and the
-        // first backward slices once the forward window reaches the end
-        int d = kmax[1] >= 0 ? 1 : 0;
-        int k = max(kmax[d], 0);
-        int j0 = max(pf[d], NCW * (k + HELPER_LEAD));
-        int j1 = min(nsl, NCW * (k + HELPER_LEAD + HELPER_SPAN));
-        if (d == 0 && j0 >= nsl) {
-            d = 1;
-            j0 = pf[1];
-            j1 = min(nsl, NCW * (HELPER_LEAD + HELPER_SPAN));
-        }
-        if (nseen == 0 || j0 >= j1) {
-            __builtin_amdgcn_s_sleep(8);
-            continue;
-        }
-        pf[d] = j1;
-        // slice index range [lo, hi) of tasks j0 .. j1-1 in direction d
-        int lo = d == 0 ? sa + j0 : sb - j1, hi = d == 0 ? sa + j1 : sb - j0;
-        const int4 *meta = d == 0 ? A.mL : A.mU;
-        int4 m0 = meta[lo], m1 = meta[hi - 1];
-        long e0 = m0.z, e1 = (long)m1.z + (long)(m1.y >> 8) * RAS_SLICE;
-        long p0 = m0.x, p1 = (long)m1.x + (m1.y & 255);
-        int nh = A.helpers;
-        acc = touch_lines(meta, 16L * lo, 16L * hi, h, nh, acc);
-        acc = touch_lines(d == 0 ? A.lcol : A.ucol, 4 * e0, 4 * e1, h, nh, acc);
-        acc = touch_lines(d == 0 ? A.lval : A.uval, 4 * sizeof(T) * e0, 4 * sizeof(T) * e1, h, nh,
-                          acc);
-        acc = touch_lines(d == 0 ? (const T *)A.rl : (const T *)A.y, 2 * sizeof(T) * p0,
-                          2 * sizeof(T) * p1, h, nh, acc);
-        if (d == 1) acc = touch_lines(A.dinv, 4 * sizeof(T) * p0, 4 * sizeof(T) * p1, h, nh, acc);
-    }
-    // keep the loads: an impossible value is the only one ever stored
-    if (acc == 0x9e3779b9u && threadIdx.x == 0) sink[s] = acc;
-}
-
 // Forward then backward substitution of one subdomain per workgroup on the
-// gathered right-hand side; the result overwrites y in local order.  With
-// nsp = ns rounded up to 8, the grid holds the ns sweep workgroups, padding
-// up to nsp, and A.helpers groups of nsp prefetch workgroups (none unless
-// all of them fit on the device at once, one per CU): workgroup b runs on
-// XCD b mod 8, so prefetch workgroup nsp (1 + h) + s of subdomain s shares
-// the sweep's L2.
+// gathered right-hand side; the result overwrites y in local order.
 template <class T>
 __global__ __launch_bounds__(SWG) void k_ras_sweep(SweepArgs<T> A) {
     constexpr int R = RingSize<T>::rows;
     __shared__ int lp[MAXLEV + 1];
     __shared__ int maxw;
     __shared__ __attribute__((aligned(16))) T ring[2 * R];
-    if ((int)blockIdx.x >= A.ns) {
-        int nsp = (A.ns + 7) & ~7;
-        int b = (int)blockIdx.x - nsp;
-        if (b >= 0 && b % nsp < A.ns)
-            ras_helper<T>(A, b % nsp, b / nsp, (unsigned *)(A.prog + A.ns * NCW));
-        return;
-    }
     int s = blockIdx.x;
     int nlev = A.nlev[s], base = A.lbase[s];
     if (threadIdx.x == 0) maxw = 0;
@@ -866,8 +756,6 @@ __global__ __launch_bounds__(SWG) void k_ras_sweep(SweepArgs<T> A) {
     int lane = threadIdx.x & 63;
     sweep_dir<T, true>(A, lp, ring, win, sa, sb, nlev, wave, lane);
     sweep_dir<T, false>(A, lp, ring, win, sa, sb, nlev, wave, lane);
-    __hip_atomic_store(&A.prog[s * NCW + wave], (int)stamp(A.epoch, STAMP_DONE), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_slice_meta(int nslice, const int *st, const int *cn, const int *wl,
@@ -901,8 +789,6 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     R2P_TRY(D.sl_of.ensure(mtot));
     R2P_TRY(D.dsrc_pos.ensure(mtot));
     R2P_TRY(D.counters.ensure(64 + 2 * ns));
-    R2P_TRY(D.prog.ensure((size_t)ns * (NCW + 1)));
-    R2P_HIP(hipMemsetAsync(D.prog.p, 0, sizeof(int) * (size_t)ns * (NCW + 1), s));
     R2P_TRY(P->pin.ensure(1 << 16));
     int nb = r2p_blocks(mtot, BS);
     // 1. levels of the dependency graph
@@ -1082,11 +968,7 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     A.mtot = mtot;
     int ns = P->rs.ns;
     A.ns = ns;
-    A.prog = D.prog.p;
-    A.epoch = ++D.epoch;
-    int nsp = (ns + 7) & ~7;
-    A.helpers = (1 + HELPERS) * nsp <= r2p_cu_count() ? HELPERS : 0;
-    k_ras_sweep<T><<<nsp * (1 + A.helpers), SWG, 0, s>>>(A);
+    k_ras_sweep<T><<<ns, SWG, 0, s>>>(A);
     R2P_LAUNCH();
     k_ras_scatter<T><<<nb, BS, 0, s>>>(mtot, P->J->m->ph.n, D.glob.p, D.owned.p, y, xp,
                                        accumulate, out);
