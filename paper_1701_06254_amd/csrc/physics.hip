@@ -14,6 +14,7 @@
 //
 // This file is compiled without floating-point contraction so the property
 // and flux arithmetic (and with it every upstream decision) is reproducible.
+#include <atomic>
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -121,6 +122,8 @@ extern "C" int r2p_model_create(const r2p_model_desc *d, r2p_model **out) {
     }
     R2P_HIP(hipSetDevice(d->device));
     r2p_model *m = new r2p_model();
+    static std::atomic<unsigned long long> next_serial{1};
+    m->serial = next_serial++;
     m->dev = d->device;
     Phys &P = m->ph;
     P.nx = d->nx; P.ny = d->ny; P.nz = d->nz; P.n = (int)n; P.nw = d->nw; P.nperf = nperf;
@@ -180,6 +183,7 @@ extern "C" int r2p_model_create(const r2p_model_desc *d, r2p_model **out) {
 }
 
 extern "C" int r2p_model_destroy(r2p_model *m) {
+    if (m) r2p_newton_work_free(m->newton);
     delete m;
     return 0;
 }
@@ -440,6 +444,7 @@ extern "C" int r2p_jacobian_create(r2p_model *m, r2p_jacobian **out) {
     if (!m || !out) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
     r2p_jacobian *J = new r2p_jacobian();
     J->m = m;
+    J->serial = m->serial;
     long n = m->ph.n;
     int rc;
     if ((rc = J->vp.ensure(7 * n)) || (rc = J->vs.ensure(7 * n)) || (rc = J->cw.ensure(m->ph.nperf)) ||
@@ -459,7 +464,10 @@ extern "C" int r2p_jacobian_destroy(r2p_jacobian *J) {
 
 extern "C" int r2p_assemble_jacobian(r2p_model *m, const double *x, const double *x_old, double dt,
                                      r2p_jacobian *J, double *b, void *stream) {
-    if (!m || !x || !x_old || !J || !b || J->m != m) { r2p_set_error("NULL or mismatched argument"); return R2P_EINVAL; }
+    if (!m || !x || !x_old || !J || !b || J->m != m || J->serial != m->serial) {
+        r2p_set_error("NULL argument, or a Jacobian created for another model");
+        return R2P_EINVAL;
+    }
     if (!(dt > 0)) { r2p_set_error("dt must be > 0"); return R2P_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
     AsmArgs A;

@@ -70,8 +70,13 @@ struct Phys {
     double beta, alpha, rho_o, rho_w, p_ref, z_ref, c_o, c_w, c_r, mu_o, mu_w, grav;
 };
 
+struct NewtonWork;
+void r2p_newton_work_free(NewtonWork *W);
+
 struct r2p_model {
     int dev = 0;
+    unsigned long long serial = 0;     // unique over the process: caches are keyed by it
+    NewtonWork *newton = nullptr;      // workspace of r2p_newton_step, freed with the model
     Phys ph{};
     // device arrays
     DBuf<double> kx, ky, kz, phi;      // n
@@ -97,6 +102,7 @@ struct r2p_model {
 // vp[slot*n + c].
 struct r2p_jacobian {
     r2p_model *m = nullptr;
+    unsigned long long serial = 0;      // serial of the model it was created for
     DBuf<double2> vp, vs;   // 7n
     DBuf<double2> cw;       // nperf: d(cell oil, water eq)/d p_b
     DBuf<double2> wc;       // nperf: d(well eq)/d(p_cell, s_cell)
@@ -239,8 +245,9 @@ struct r2p_cpr {
     DBuf<double> lu;         // coarsest dense LU scratch
     DBuf<int> piv;
     DBuf<int> status;        // device status flags
-    // level-0 structure cache
+    // level-0 structure cache, and the model the cached structures belong to
     int app_n = -1;
+    unsigned long long serial = 0;
     // work vectors
     DBuf<double> t_r, t_y, t_xp, t_ras, t_rl;
     DBuf<float> t_rasf, t_rlf;

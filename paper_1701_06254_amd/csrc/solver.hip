@@ -259,9 +259,13 @@ extern "C" int r2p_setup_cpr(r2p_jacobian *J, const r2p_cpr_opts *o, r2p_cpr *P,
     R2P_TRY(check_opts(o));
     if (J->state != 1) { r2p_set_error("Jacobian not assembled since its last set-up"); return R2P_ESTATE; }
     hipStream_t s = (hipStream_t)stream;
-    if (P->J && (P->J->m != J->m || P->o.px != o->px || P->o.py != o->py || P->o.overlap != o->overlap))
+    // cached structures belong to one model (by serial: a model allocated
+    // where a destroyed one was is another model)
+    if (P->serial != J->m->serial || P->o.px != o->px || P->o.py != o->py ||
+        P->o.overlap != o->overlap)
         P->rs.ns = 0;   // membership must be rebuilt
-    if (P->J && P->J->m != J->m) P->app_n = -1;
+    if (P->serial != J->m->serial) P->app_n = -1;
+    P->serial = J->m->serial;
     P->ready = 0;
     P->J = J;
     P->o = *o;
@@ -549,6 +553,8 @@ struct NewtonWork {
     }
 };
 
+void r2p_newton_work_free(NewtonWork *W) { delete W; }
+
 static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -620,14 +626,16 @@ extern "C" int r2p_newton_step(r2p_model *m, double *x, double dt, const double 
     }
     R2P_TRY(check_opts(&o->cpr));
     hipStream_t s = (hipStream_t)stream;
-    static thread_local NewtonWork *W = nullptr;
-    if (!W || W->m != m) {
-        delete W;
-        W = new NewtonWork();
-        W->m = m;
-        R2P_TRY(r2p_jacobian_create(m, &W->J));
-        R2P_TRY(r2p_cpr_create(&W->P));
+    // the workspace (Jacobian, CPR, vectors) belongs to the model
+    if (!m->newton) {
+        NewtonWork *W0 = new NewtonWork();
+        W0->m = m;
+        int rc = r2p_jacobian_create(m, &W0->J);
+        if (!rc) rc = r2p_cpr_create(&W0->P);
+        if (rc) { delete W0; return rc; }
+        m->newton = W0;
     }
+    NewtonWork *W = m->newton;
     long N = 2L * (m->ph.n + m->ph.nw);
     R2P_TRY(W->xold.ensure(N));
     R2P_TRY(W->xk.ensure(N));
