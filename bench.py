@@ -419,6 +419,26 @@ def large_run(args, w, log):
     mem64 = used_gib()
     s64 = summarise(recs)
     accepted = [r["dt"] for r in recs if r["status"] == 0]
+    out = {
+        "metric": METRIC, "value": round(s64["solve_ms"], 3), "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms64, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w['name']}: {model.n} cells, {len(w['wells'])} wells, "
+                               f"channelised permeability; dt from {DT_INIT} d; CPR two-stage, "
+                               f"QI + local potential order, RAS {px}x{py} overlap 1 BILU(0), "
+                               "aggregation AMG V(1,1), FGMRES(30) rtol 1e-8",
+                   "cells": model.n, "subdomains": px * py},
+        "dt_days": accepted,
+        "newton_its_per_step": round(s64["solves"] / args.steps, 2),
+        "linear_its_per_solve": round(s64["its_per_solve"], 2),
+        "setup_ms_per_solve": round(s64["setup_ms"], 3),
+        "device_memory_gib": mem64,
+        "kernels": kern,
+        "fp32_learned": None,
+    }
+    if args.no_learned:
+        return out
 
     t1 = time.perf_counter()
     pairs = []
@@ -462,23 +482,7 @@ def large_run(args, w, log):
     n = model.n
     p64, s_64 = x[0:2 * n:2], x[1:2 * n:2]
     pl, s_l = xl[0:2 * n:2], xl[1:2 * n:2]
-    return {
-        "metric": METRIC, "value": round(s64["solve_ms"], 3), "unit": "ms", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms64, 3),
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{w['name']}: {n} cells, {len(w['wells'])} wells, channelised "
-                               f"permeability; dt from {DT_INIT} d; CPR two-stage, QI + local "
-                               f"potential order, RAS {px}x{py} overlap 1 BILU(0), aggregation "
-                               "AMG V(1,1), FGMRES(30) rtol 1e-8",
-                   "cells": n, "subdomains": px * py},
-        "dt_days": accepted,
-        "newton_its_per_step": round(s64["solves"] / args.steps, 2),
-        "linear_its_per_solve": round(s64["its_per_solve"], 2),
-        "setup_ms_per_solve": round(s64["setup_ms"], 3),
-        "device_memory_gib": mem64,
-        "kernels": kern,
-        "fp32_learned": {
+    out["fp32_learned"] = {
             "ms_per_step": round(msl, 3), "solve_ms": round(sl["solve_ms"], 3),
             "newton_its": sl["solves"], "linear_its_per_solve": round(sl["its_per_solve"], 2),
             "guess_taken": int(sum(r["used"] for r in recsl)), "steps": len(recsl),
@@ -490,8 +494,8 @@ def large_run(args, w, log):
             "training": {"models": args.train_models, "adam_steps": args.train_iters,
                          "seconds": round(train_s, 1),
                          "loss_first20": float(np.mean(losses[:20])),
-                         "loss_last20": float(np.mean(losses[-20:]))}},
-    }
+                         "loss_last20": float(np.mean(losses[-20:]))}}
+    return out
 
 
 def main():
