@@ -663,12 +663,13 @@ __global__ __launch_bounds__(256) void k_csr_level(CsrArgs<T> A) {
 }
 
 // Restriction P^T r: a group of GR lanes per coarse row (lanes stride over
-// the members, then a fixed butterfly; aggregates average 2-4 members);
+// the members two at a time, then a fixed butterfly; aggregates average 2-4
+// members);
 // aggregates with more than BIG members (up to about a thousand on the
 // coarse levels) get a wavefront each in trailing workgroups, four members
 // per lane in flight.  When the coarse level is smoothed (xc given), its
 // pre-smoothed iterate b / d is formed here.
-constexpr int GR = 4;
+constexpr int GR = 2;
 template <class T>
 __global__ __launch_bounds__(256) void k_restrict(int nc, int nbs, const int *mptr, const int *mem,
                                                   const int *big, int nbig, const T *r, T *bc,
@@ -681,7 +682,13 @@ __global__ __launch_bounds__(256) void k_restrict(int nc, int nbs, const int *mp
         if (I >= nc) return;
         int a = mptr[I], b = mptr[I + 1];
         if (b - a > BIG) return;
-        for (int t = a + lane0; t < b; t += GR) acc += r[mem[t]];
+        // two members per lane in flight
+        for (int t = a + lane0; t < b; t += 2 * GR) {
+            int tb = t + GR < b ? t + GR : t;
+            int ma = mem[t], mb = mem[tb];
+            T ra = r[ma], rb = r[mb];
+            acc += ra + (t + GR < b ? rb : (T)0);
+        }
 #pragma unroll
         for (int d = 1; d < GR; d <<= 1) acc += __shfl_xor(acc, d, 64);
     } else {
