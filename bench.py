@@ -301,6 +301,7 @@ def learned_run(args, model, x0, x64, dts, form, log):
     feat = r2p.cnn_features(model, x0, dts[0])
     g = model.w["grid"]
     shape = (1, g["nz"], g["ny"], g["nx"])
+    net.forward(feat, shape)            # sizes the activation buffers for this grid
     t_fwd = time_on_stream(lambda: net.forward(feat, shape), 5)
     flop = 2 * 27 * (6 * 32 + 8 * 32 * 32 + 32 * 2) * model.n
     o = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, precision=r2p.FP32),
