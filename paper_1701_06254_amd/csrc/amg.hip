@@ -366,7 +366,7 @@ __global__ __launch_bounds__(1024) void k_dense_lu_inv(int n, double *a, int *pi
 // Member lists (CSR, ascending) of the nc aggregates of agg[0..n).
 static int build_members(r2p_cpr *P, int n, const int *agg, int nc, DBuf<int> &mptr,
                          DBuf<int> &mem, hipStream_t s) {
-    SetupWork &W = P->ws;
+    SetupWork &W = P->aws;
     DBuf<unsigned> &key = W.u[0], &kt = W.u[1], &vt = W.u[2];
     DBuf<int> &hist = W.i[0];
     R2P_TRY(mptr.ensure(nc + 1));
@@ -377,8 +377,8 @@ static int build_members(r2p_cpr *P, int n, const int *agg, int nc, DBuf<int> &m
     unsigned *val = (unsigned *)mem.p;
     k_member_keys<<<r2p_blocks(n, BS), BS, 0, s>>>(n, agg, key.p, val);
     R2P_LAUNCH();
-    R2P_TRY(r2p_sort_pairs(key.p, val, kt.p, vt.p, n, r2p_bits_for(nc), hist, P->iscratch,
-                           P->pin, s));
+    R2P_TRY(r2p_sort_pairs(key.p, val, kt.p, vt.p, n, r2p_bits_for(nc), hist, P->aiscratch,
+                           P->apin, s));
     k_member_ptr<<<r2p_blocks(n, BS), BS, 0, s>>>(n, nc, key.p, mptr.p);
     R2P_LAUNCH();
     R2P_HIP(hipStreamSynchronize(s));
@@ -388,7 +388,7 @@ static int build_members(r2p_cpr *P, int n, const int *agg, int nc, DBuf<int> &m
 static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, const double *val,
                     const int *agg, int nc, DBuf<int> &rpc, DBuf<int> &colc, DBuf<double> &valc,
                     int *nnzc, hipStream_t s) {
-    SetupWork &W = P->ws;
+    SetupWork &W = P->aws;
     DBuf<unsigned> &keyI = W.u[0], &keyJz = W.u[1], &keyIs = W.u[2], &idx = W.u[3], &kt = W.u[4],
                    &vt = W.u[5];
     DBuf<int> &flag = W.i[0], &hist = W.i[1];
@@ -405,10 +405,10 @@ static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, c
     // stable by coarse column, then stable by coarse row
     R2P_HIP(hipMemcpyAsync(kt.p, keyJz.p, sizeof(unsigned) * nnz, hipMemcpyDeviceToDevice, s));
     R2P_HIP(hipMemcpyAsync(keyIs.p, kt.p, sizeof(unsigned) * nnz, hipMemcpyDeviceToDevice, s));
-    R2P_TRY(r2p_sort_pairs(keyIs.p, idx.p, kt.p, vt.p, nnz, bits, hist, P->iscratch, P->pin, s));
+    R2P_TRY(r2p_sort_pairs(keyIs.p, idx.p, kt.p, vt.p, nnz, bits, hist, P->aiscratch, P->apin, s));
     k_gather_u<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, idx.p, keyI.p, keyIs.p);
     R2P_LAUNCH();
-    R2P_TRY(r2p_sort_pairs(keyIs.p, idx.p, kt.p, vt.p, nnz, bits, hist, P->iscratch, P->pin, s));
+    R2P_TRY(r2p_sort_pairs(keyIs.p, idx.p, kt.p, vt.p, nnz, bits, hist, P->aiscratch, P->apin, s));
     // the coarse columns in sorted order, gathered once (kt is free again)
     k_gather_u<<<r2p_blocks(nnz, BS), BS, 0, s>>>(nnz, idx.p, keyJz.p, kt.p);
     R2P_LAUNCH();
@@ -416,7 +416,7 @@ static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, c
     R2P_LAUNCH();
     R2P_HIP(hipMemsetAsync(flag.p + nnz, 0, sizeof(int), s));
     int nnz_c = 0;
-    R2P_TRY(r2p_scan_int(flag.p, flag.p, nnz + 1, &nnz_c, P->iscratch, P->pin, s));
+    R2P_TRY(r2p_scan_int(flag.p, flag.p, nnz + 1, &nnz_c, P->aiscratch, P->apin, s));
     R2P_TRY(rpc.ensure(nc + 1));
     R2P_TRY(colc.ensure(nnz_c));
     R2P_TRY(valc.ensure(nnz_c));
@@ -436,7 +436,7 @@ static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, c
 // One aggregation pass: agg (row -> aggregate) and the aggregate count.
 static int aggregate_pass(r2p_cpr *P, int n, const int *rp, const int *col, const double *val,
                           DBuf<int> &agg, int *nc, hipStream_t s) {
-    SetupWork &W = P->ws;
+    SetupWork &W = P->aws;
     DBuf<double> &thr = W.d[0];
     DBuf<int> &match = W.i[0], &prop = W.i[1], &flag = W.i[2], &jt = W.i[3];
     R2P_TRY(thr.ensure(n));
@@ -459,7 +459,7 @@ static int aggregate_pass(r2p_cpr *P, int n, const int *rp, const int *col, cons
     R2P_LAUNCH();
     R2P_HIP(hipMemsetAsync(flag.p + n, 0, sizeof(int), s));
     int cnt = 0;
-    R2P_TRY(r2p_scan_int(flag.p, flag.p, n + 1, &cnt, P->iscratch, P->pin, s));
+    R2P_TRY(r2p_scan_int(flag.p, flag.p, n + 1, &cnt, P->aiscratch, P->apin, s));
     R2P_TRY(agg.ensure(n));
     k_number<<<nb, BS, 0, s>>>(n, match.p, jt.p, flag.p, agg.p);
     R2P_LAUNCH();
@@ -471,12 +471,12 @@ static int aggregate_pass(r2p_cpr *P, int n, const int *rp, const int *col, cons
 // List (ascending) of the rows i < n with ptr[i+1] - ptr[i] > thr.
 static int long_rows(r2p_cpr *P, int n, const int *ptr, int thr, DBuf<int> &list, int *count,
                      hipStream_t s) {
-    DBuf<int> &flag = P->ws.i[0];
+    DBuf<int> &flag = P->aws.i[0];
     R2P_TRY(flag.ensure(n + 1));
     k_long_flag<<<r2p_blocks(n + 1, BS), BS, 0, s>>>(n, ptr, thr, flag.p);
     R2P_LAUNCH();
     int cnt = 0;
-    R2P_TRY(r2p_scan_int(flag.p, flag.p, n + 1, &cnt, P->iscratch, P->pin, s));
+    R2P_TRY(r2p_scan_int(flag.p, flag.p, n + 1, &cnt, P->aiscratch, P->apin, s));
     R2P_TRY(list.ensure(cnt));
     k_long_list<<<r2p_blocks(n, BS), BS, 0, s>>>(n, ptr, thr, flag.p, list.p);
     R2P_LAUNCH();
@@ -497,7 +497,7 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
         R2P_LAUNCH();
         R2P_HIP(hipMemsetAsync(L0.rp.p + n, 0, sizeof(int), s));
         int nnz = 0;
-        R2P_TRY(r2p_scan_int(L0.rp.p, L0.rp.p, n + 1, &nnz, P->iscratch, P->pin, s));
+        R2P_TRY(r2p_scan_int(L0.rp.p, L0.rp.p, n + 1, &nnz, P->aiscratch, P->apin, s));
         R2P_TRY(L0.col.ensure(nnz));
         R2P_TRY(P->iscratch2.ensure(nnz));
         k_app_cols<<<r2p_blocks(n, BS), BS, 0, s>>>(ph, L0.rp.p, L0.col.p, P->iscratch2.p);
@@ -527,13 +527,13 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
         k_iota<<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, A.agg.p);
         R2P_LAUNCH();
         // successive passes, each on the Galerkin product of the previous one
-        DBuf<int> *crp = P->ws.crp, *ccol = P->ws.ccol;
-        DBuf<double> *cval = P->ws.cval;
+        DBuf<int> *crp = P->aws.crp, *ccol = P->aws.ccol;
+        DBuf<double> *cval = P->aws.cval;
         const int *rp = A.rp.p, *col = A.col.p;
         const double *val = A.val.p;
         int cn = A.n, nc = A.n, nnzc = 0, cnnz = A.nnz;
         for (int p = 0; p < passes; p++) {
-            DBuf<int> &a = P->ws.agg;
+            DBuf<int> &a = P->aws.agg;
             R2P_TRY(aggregate_pass(P, cn, rp, col, val, a, &nc, s));
             bool last = p == passes - 1;
             DBuf<int> &orp = last ? C.rp : crp[p & 1];
@@ -585,14 +585,15 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
     R2P_TRY(P->lu.ensure((size_t)nc * nc));
     R2P_TRY(P->cinv.ensure((size_t)nc * nc));
     R2P_TRY(P->piv.ensure(nc));
-    R2P_TRY(P->status.ensure(4));
-    R2P_HIP(hipMemsetAsync(P->status.p + 1, 0, sizeof(int), s));
+    R2P_TRY(P->astatus.ensure(1));
+    R2P_TRY(P->apin.ensure(64));
+    R2P_HIP(hipMemsetAsync(P->astatus.p, 0, sizeof(int), s));
     k_to_dense<<<r2p_blocks(nc, BS), BS, 0, s>>>(nc, C.rp.p, C.col.p, C.val.p, P->lu.p);
     R2P_LAUNCH();
-    k_dense_lu_inv<<<1, 1024, 0, s>>>(nc, P->lu.p, P->piv.p, P->cinv.p, P->status.p + 1);
+    k_dense_lu_inv<<<1, 1024, 0, s>>>(nc, P->lu.p, P->piv.p, P->cinv.p, P->astatus.p);
     R2P_LAUNCH();
-    int *h = (int *)P->pin.p;
-    R2P_HIP(hipMemcpyAsync(h, P->status.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    int *h = (int *)P->apin.p;
+    R2P_HIP(hipMemcpyAsync(h, P->astatus.p, sizeof(int), hipMemcpyDeviceToHost, s));
     R2P_HIP(hipStreamSynchronize(s));
     if (*h) { r2p_set_error("coarsest AMG matrix is singular"); return R2P_ESINGULAR; }
     return 0;

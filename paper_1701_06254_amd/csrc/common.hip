@@ -1,5 +1,6 @@
 // Error reporting, device/pinned buffers and a device exclusive scan.
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstring>
 
@@ -256,13 +257,13 @@ int r2p_scan_int(const int *in, int *out, int n, int *total_host, DBuf<int> &tmp
 }
 
 int r2p_cu_count() {
-    static int cache[64] = {0};
+    static std::atomic<int> cache[64];   // zero-initialised (static storage)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-    if (!cache[dev]) {
-        int n = 0;
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 0;
-        cache[dev] = n;
+    int c = cache[dev].load(std::memory_order_relaxed);
+    if (!c) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) c = 0;
+        cache[dev].store(c, std::memory_order_relaxed);
     }
-    return cache[dev];
+    return c;
 }

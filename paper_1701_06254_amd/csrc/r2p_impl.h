@@ -255,6 +255,15 @@ struct r2p_cpr {
     DBuf<int> iscratch2;
     DBuf<double> dscratch;
     HostPinned pin;
+    // The AMG set-up runs on a host thread and stream of its own beside the
+    // RAS set-up, so it owns its scratch, pinned word and status flag.
+    SetupWork aws;
+    DBuf<int> aiscratch;
+    DBuf<int> astatus;
+    HostPinned apin;
+    hipStream_t as = nullptr;            // non-blocking, default priority
+    hipEvent_t aev[2] = {nullptr, nullptr};
+    ~r2p_cpr();
 };
 
 // ------------------------------------------------------------ utilities

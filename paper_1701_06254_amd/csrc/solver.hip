@@ -17,6 +17,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
 
 #include "r2p_impl.h"
 
@@ -242,6 +244,67 @@ extern "C" int r2p_cpr_destroy(r2p_cpr *P) {
     return 0;
 }
 
+r2p_cpr::~r2p_cpr() {
+    for (hipEvent_t &e : aev)
+        if (e) (void)hipEventDestroy(e);
+    if (as) (void)hipStreamDestroy(as);
+}
+
+// The second stream and its two events, made on the first set-up.
+static int ensure_amg_stream(r2p_cpr *P) {
+    if (!P->as) R2P_HIP(hipStreamCreateWithFlags(&P->as, hipStreamNonBlocking));
+    for (hipEvent_t &e : P->aev)
+        if (!e) R2P_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return 0;
+}
+
+// The RAS and AMG set-ups read the decoupled Jacobian and write disjoint
+// parts of the handle; each waits on the host for its own scan totals.
+// The AMG set-up runs on a worker thread and its own stream (after the
+// decoupling on s), the RAS set-up on s in this thread, so that the one's
+// host waits and narrow kernels (one workgroup per subdomain) overlap the
+// other's work.  Both are joined before return, and s then waits for the
+// AMG stream.
+static int setup_both(r2p_cpr *P, hipStream_t s) {
+    R2P_TRY(ensure_amg_stream(P));
+    int dev = 0;
+    R2P_HIP(hipGetDevice(&dev));
+    R2P_HIP(hipEventRecord(P->aev[0], s));
+    R2P_HIP(hipStreamWaitEvent(P->as, P->aev[0], 0));
+    int rc_amg = 0;
+    std::string err_amg;
+    auto amg = [&] {
+        if (hipSetDevice(dev) != hipSuccess) {
+            rc_amg = R2P_EHIP;
+            err_amg = "hipSetDevice failed on the AMG set-up thread";
+            return;
+        }
+        rc_amg = r2p_amg_setup(P, P->as);
+        if (rc_amg) err_amg = r2p_last_error();
+    };
+    std::thread t;
+    bool threaded = true;
+    try {
+        t = std::thread(amg);
+    } catch (...) {
+        threaded = false;
+    }
+    int rc = r2p_ras_setup(P, s);
+    if (threaded) t.join();
+    else if (!rc) amg();
+    if (!rc && rc_amg) {
+        r2p_set_error("%s", err_amg.c_str());
+        rc = rc_amg;
+    }
+    if (rc) {
+        (void)hipStreamSynchronize(P->as);
+        return rc;
+    }
+    R2P_HIP(hipEventRecord(P->aev[1], P->as));
+    R2P_HIP(hipStreamWaitEvent(s, P->aev[1], 0));
+    return 0;
+}
+
 static int check_opts(const r2p_cpr_opts *o) {
     if (o->decouple < 0 || o->decouple > 2 || o->order < 0 || o->order > 1 || o->form < 0 ||
         o->form > 1 || o->px < 1 || o->py < 1 || o->px * o->py > 256 || o->overlap < 0 ||
@@ -275,8 +338,7 @@ extern "C" int r2p_setup_cpr(r2p_jacobian *J, const r2p_cpr_opts *o, r2p_cpr *P,
     R2P_TRY(P->t_y.ensure(N));
     R2P_TRY(P->t_xp.ensure(ph.n));
     R2P_TRY(r2p_decouple_jacobian(J, o->decouple, s));
-    R2P_TRY(r2p_ras_setup(P, s));
-    R2P_TRY(r2p_amg_setup(P, s));
+    R2P_TRY(setup_both(P, s));
     P->ready = 1;
     return 0;
 }
