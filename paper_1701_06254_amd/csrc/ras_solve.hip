@@ -374,46 +374,98 @@ __device__ __forceinline__ void sub_prod(double *t, const double *l, const doubl
     t[3] -= l[2] * u[1] + l[3] * u[3];
 }
 
-__global__ __launch_bounds__(WG) void k_bilu0(FactArgs A) {
+__device__ __forceinline__ void ld4(double *v, const double *p) {
+    const double2 a = ((const double2 *)p)[0], b = ((const double2 *)p)[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
+// L entry e of row p (block a = A_pq, pivot dk = D_q^-1, ud = U_qp if kd >=
+// 0): the multiplier l = A_pq D_q^-1 replaces A_pq, then every later entry of
+// row p that row q's U part reaches loses l times that U block, in the row's
+// order (the remaining L entries, the diagonal, the U entries).
+__device__ __forceinline__ void bilu_entry(const FactArgs &A, long bl, long bu, int nlp, int e,
+                                           const double *a, const double *dk, int kd,
+                                           const double *ud, double *d, int &xi, int xe) {
+    double l[4];
+    l[0] = a[0] * dk[0] + a[1] * dk[2];
+    l[1] = a[0] * dk[1] + a[1] * dk[3];
+    l[2] = a[2] * dk[0] + a[3] * dk[2];
+    l[3] = a[2] * dk[1] + a[3] * dk[3];
+    double2 *o = (double2 *)&A.lval[4 * ent(bl, e)];
+    o[0] = make_double2(l[0], l[1]);
+    o[1] = make_double2(l[2], l[3]);
+    for (; xi < xe; xi++) {
+        int4 m = A.xl[xi];
+        if (m.x != e || m.y > nlp) break;
+        sub_prod(&A.lval[4 * ent(bl, m.y)], l, &A.uval[4 * (long)m.z]);
+    }
+    if (kd >= 0) sub_prod(d, l, ud);
+    for (; xi < xe; xi++) {
+        int4 m = A.xl[xi];
+        if (m.x != e) break;
+        sub_prod(&A.uval[4 * ent(bu, m.y - nlp - 1)], l, &A.uval[4 * (long)m.z]);
+    }
+}
+
+// Rows of one level are factorised together, one lane per row, the levels in
+// turn.  A row's wait on earlier rows is one round of loads: its own first
+// LPF L blocks, their columns and U_qp slots (the row's own data, which no
+// other row changes) are requested together, then together the pivots and
+// U_qp blocks of the rows they name (final since those rows' levels), and
+// only then is any of them used.  Entries past LPF load theirs in turn.
+constexpr int LPF = 4;
+constexpr int BWG = 512;              // 8 waves: registers for the prefetched blocks
+
+__global__ __launch_bounds__(BWG) void k_bilu0(FactArgs A) {
     int s = blockIdx.x;
     int nlev = A.nlev[s], base = A.lbase[s];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int L = 0; L < nlev; L++) {
         int s0 = A.soff[base + L], s1 = A.soff[base + L + 1];
-        for (int sl = s0 + wave; sl < s1; sl += NWAVE) {
+        for (int sl = s0 + wave; sl < s1; sl += BWG / 64) {
             if (lane >= A.sl_cn[sl]) continue;
             int p = A.sl_st[sl] + lane;
             long bl = ras_entry(A.sl_bl[sl], lane, 0), bu = ras_entry(A.sl_bu[sl], lane, 0);
             int nlp = A.nl[p];
             int xi = A.xptr[p], xe = A.xptr[p + 1];
+            // an extra match of an earlier entry may change a later L block
+            bool reread = xi < xe;
             double *dp = &A.dinv[4 * (long)p];
-            double d[4] = {dp[0], dp[1], dp[2], dp[3]};
-            for (int e = 0; e < nlp; e++) {
+            double d[4];
+            ld4(d, dp);
+            int q[LPF], kd[LPF];
+            double a[LPF][4], dk[LPF][4], ud[LPF][4];
+#pragma unroll
+            for (int e = 0; e < LPF; e++) {
+                if (e < nlp) {
+                    long k = ent(bl, e);
+                    q[e] = A.lcol[k];
+                    kd[e] = A.ldiag[k];
+                    ld4(a[e], &A.lval[4 * k]);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < LPF; e++) {
+                if (e < nlp) {
+                    ld4(dk[e], &A.dinv[4 * (long)q[e]]);
+                    if (kd[e] >= 0) ld4(ud[e], &A.uval[4 * (long)kd[e]]);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < LPF; e++) {
+                if (e < nlp) {
+                    if (reread) ld4(a[e], &A.lval[4 * ent(bl, e)]);
+                    bilu_entry(A, bl, bu, nlp, e, a[e], dk[e], kd[e], ud[e], d, xi, xe);
+                }
+            }
+            for (int e = LPF; e < nlp; e++) {
                 long k = ent(bl, e);
-                int q = A.lcol[k];
-                double *a = &A.lval[4 * k];
-                const double *dk = &A.dinv[4 * (long)q];
-                double l[4];
-                l[0] = a[0] * dk[0] + a[1] * dk[2];
-                l[1] = a[0] * dk[1] + a[1] * dk[3];
-                l[2] = a[2] * dk[0] + a[3] * dk[2];
-                l[3] = a[2] * dk[1] + a[3] * dk[3];
-                a[0] = l[0]; a[1] = l[1]; a[2] = l[2]; a[3] = l[3];
-                // later entries of row p in order: remaining L entries, the
-                // diagonal, U entries (each target is touched once per e)
-                for (; xi < xe; xi++) {
-                    int4 m = A.xl[xi];
-                    if (m.x != e || m.y > nlp) break;
-                    sub_prod(&A.lval[4 * ent(bl, m.y)], l, &A.uval[4 * (long)m.z]);
-                }
-                int kd = A.ldiag[k];
-                if (kd >= 0) sub_prod(d, l, &A.uval[4 * (long)kd]);
-                for (; xi < xe; xi++) {
-                    int4 m = A.xl[xi];
-                    if (m.x != e) break;
-                    sub_prod(&A.uval[4 * ent(bu, m.y - nlp - 1)], l,
-                             &A.uval[4 * (long)m.z]);
-                }
+                int qe = A.lcol[k], kde = A.ldiag[k];
+                double ae[4], dke[4], ude[4];
+                ld4(ae, &A.lval[4 * k]);
+                ld4(dke, &A.dinv[4 * (long)qe]);
+                if (kde >= 0) ld4(ude, &A.uval[4 * (long)kde]);
+                bilu_entry(A, bl, bu, nlp, e, ae, dke, kde, ude, d, xi, xe);
             }
             double det = d[0] * d[3] - d[1] * d[2];
             if (det == 0.0 || det != det) atomicOr(A.status, 1);
@@ -923,7 +975,7 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     F.xl = D.xl.p;
     k_bilu_sym<<<nb, BS, 0, s>>>(mtot, F, 1);
     R2P_LAUNCH();
-    k_bilu0<<<ns, WG, 0, s>>>(F);
+    k_bilu0<<<ns, BWG, 0, s>>>(F);
     R2P_LAUNCH();
     if (P->o.precision == R2P_FP32) {
         long nlp = 4L * (nle + RAS_PAD), nup = 4L * (nue + RAS_PAD);
