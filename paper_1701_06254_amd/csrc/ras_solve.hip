@@ -234,13 +234,11 @@ __global__ void k_slice_size(int nslice, const int *w, int *sz) {
 
 // Entries of position p in its slice: predecessors and successors, each in
 // ascending local order (insertion sort over the strided slots).
-__global__ void k_fill_entries(int mtot, int n, int order, const double *phi, const int *permi,
-                               const int *glob_nat, const int *aptr, const int *adj,
+__device__ __forceinline__ void fill_row_long(int p, int n, int order, const double *phi, const int *permi,
+                              const int *glob_nat, const int *aptr, const int *adj,
                                const int *asrc, const int *pos, const int *glob, const int *sl_of,
-                               const int *sl_st, const int *sl_bl, const int *sl_bu, int *lcol,
-                               int *lsrc, int *ucol, int *usrc) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= mtot) return;
+                              const int *sl_st, const int *sl_bl, const int *sl_bu, int *lcol,
+                              int *lsrc, int *ucol, int *usrc) {
     int l = permi[p], g = glob_nat[l];
     int sl = sl_of[p], r = p - sl_st[sl];
     long bl = sl_bl[sl], bu = sl_bu[sl];
@@ -275,6 +273,88 @@ __global__ void k_fill_entries(int mtot, int n, int order, const double *phi, co
             }
             col[ras_entry(b, r, k + 1)] = vc;
             src[ras_entry(b, r, k + 1)] = vs;
+        }
+    }
+}
+
+// Placement of every local row's couplings into its L (predecessors) and U
+// (successors) entries, each part ascending in the local order.  A row with
+// at most FE couplings (every cell row) sorts them in registers: the local
+// order is a strict total order on global rows, so sorting all couplings at
+// once puts the predecessors first, both parts ascending, and the result is
+// the same as the per-part insertion sort that longer rows (wells) use.
+constexpr int FE = 8;
+
+// before() on values already loaded: cells ahead of wells, cells by
+// decreasing potential then index, wells (or the natural order) by index.
+__device__ __forceinline__ bool before_v(int h, double ph, int g, double pg, int n, int order) {
+    bool hc = h < n, gc = g < n;
+    if (hc != gc) return hc;
+    if (!hc || order == R2P_ORDER_NATURAL) return h < g;
+    return ph > pg || (ph == pg && h < g);
+}
+
+__global__ void k_fill_entries(int mtot, int n, int order, const double *phi, const int *permi,
+                               const int *glob_nat, const int *aptr, const int *adj,
+                               const int *asrc, const int *pos, const int *glob, const int *sl_of,
+                               const int *sl_st, const int *sl_bl, const int *sl_bu, int *lcol,
+                               int *lsrc, int *ucol, int *usrc) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= mtot) return;
+    int l = permi[p];
+    int t0 = aptr[l], deg = aptr[l + 1] - t0;
+    if (deg > FE) {
+        fill_row_long(p, n, order, phi, permi, glob_nat, aptr, adj, asrc, pos, glob, sl_of, sl_st,
+                      sl_bl, sl_bu, lcol, lsrc, ucol, usrc);
+        return;
+    }
+    const bool pot = order != R2P_ORDER_NATURAL;
+    int g = glob_nat[l];
+    double pg = (pot && g < n) ? phi[g] : 0.0;
+    // INT_MAX pads the unused slots: it sorts after every row
+    int gh[FE], ps[FE], sr[FE];
+    double pv[FE];
+#pragma unroll
+    for (int k = 0; k < FE; k++) {
+        gh[k] = 0x7fffffff; ps[k] = 0; sr[k] = 0; pv[k] = 0.0;
+        if (k < deg) {
+            int h = adj[t0 + k];
+            gh[k] = glob_nat[h];
+            ps[k] = pos[h];
+            sr[k] = asrc[t0 + k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < FE; k++)
+        if (pot && gh[k] < n) pv[k] = phi[gh[k]];
+    // odd-even transposition sort (FE rounds sort FE keys)
+#pragma unroll
+    for (int rd = 0; rd < FE; rd++) {
+#pragma unroll
+        for (int k = rd & 1; k + 1 < FE; k += 2) {
+            if (before_v(gh[k + 1], pv[k + 1], gh[k], pv[k], n, order)) {
+                int ti = gh[k]; gh[k] = gh[k + 1]; gh[k + 1] = ti;
+                ti = ps[k]; ps[k] = ps[k + 1]; ps[k + 1] = ti;
+                ti = sr[k]; sr[k] = sr[k + 1]; sr[k + 1] = ti;
+                double td = pv[k]; pv[k] = pv[k + 1]; pv[k + 1] = td;
+            }
+        }
+    }
+    int sl = sl_of[p], r = p - sl_st[sl];
+    long bl = sl_bl[sl], bu = sl_bu[sl];
+    int el = 0, eu = 0;
+#pragma unroll
+    for (int k = 0; k < FE; k++) {
+        if (k < deg) {
+            if (before_v(gh[k], pv[k], g, pg, n, order)) {
+                long e = ras_entry(bl, r, el++);
+                lcol[e] = ps[k];
+                lsrc[e] = sr[k];
+            } else {
+                long e = ras_entry(bu, r, eu++);
+                ucol[e] = ps[k];
+                usrc[e] = sr[k];
+            }
         }
     }
 }
