@@ -416,12 +416,8 @@ __global__ void k_bilu_gather(int mtot, FactArgs A) {
 
 // Pass 0 counts the extra matches of every position and records the
 // diagonal match of every L entry; pass 1 writes the extra matches.
-__global__ void k_bilu_sym(int mtot, FactArgs A, int pass) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= mtot) return;
-    int nlp = A.nl[p], nup = A.nu[p];
-    long bl = slice_entry(A.sl_of, A.sl_st, A.sl_bl, p, 0);
-    long bu = slice_entry(A.sl_of, A.sl_st, A.sl_bu, p, 0);
+__device__ __forceinline__ void bilu_sym_long(const FactArgs &A, int p, int nlp, int nup, long bl,
+                                              long bu, int pass) {
     int cnt = 0, out = pass ? A.xptr[p] : 0;
     for (int e = 0; e < nlp; e++) {
         long k = ent(bl, e);
@@ -441,6 +437,80 @@ __global__ void k_bilu_sym(int mtot, FactArgs A, int pass) {
                     cnt++;
                 }
                 break;
+            }
+        }
+    }
+    if (pass == 0) A.xptr[p] = cnt;
+}
+
+// Rows whose own entries and whose predecessors' U parts each fit in SE
+// slots (every cell row) hold them in registers: the predecessors' U column
+// lists are all requested before the matching starts, and the matches come
+// out in the same order (by L entry, then by later entry) as the general
+// loop's.
+constexpr int SE = 8;
+
+__global__ void k_bilu_sym(int mtot, FactArgs A, int pass) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= mtot) return;
+    int nlp = A.nl[p], nup = A.nu[p];
+    long bl = slice_entry(A.sl_of, A.sl_st, A.sl_bl, p, 0);
+    long bu = slice_entry(A.sl_of, A.sl_st, A.sl_bu, p, 0);
+    if (nlp + nup > SE) {
+        bilu_sym_long(A, p, nlp, nup, bl, bu, pass);
+        return;
+    }
+    // the row's entries in order: L columns, p itself, U columns
+    int c[SE + 1];
+#pragma unroll
+    for (int k = 0; k <= SE; k++) {
+        c[k] = -1;
+        if (k < nlp) c[k] = A.lcol[ent(bl, k)];
+        else if (k == nlp) c[k] = p;
+        else if (k <= nlp + nup) c[k] = A.ucol[ent(bu, k - nlp - 1)];
+    }
+    long buq[SE];
+    int nuq[SE];
+#pragma unroll
+    for (int e = 0; e < SE; e++) {
+        buq[e] = 0;
+        nuq[e] = 0;
+        if (e < nlp) {
+            buq[e] = slice_entry(A.sl_of, A.sl_st, A.sl_bu, c[e], 0);
+            nuq[e] = A.nu[c[e]];
+        }
+    }
+    bool fits = true;
+#pragma unroll
+    for (int e = 0; e < SE; e++) fits = fits && nuq[e] <= SE;
+    if (!fits) {
+        bilu_sym_long(A, p, nlp, nup, bl, bu, pass);
+        return;
+    }
+    int u[SE][SE];
+#pragma unroll
+    for (int e = 0; e < SE; e++)
+#pragma unroll
+        for (int y = 0; y < SE; y++)
+            u[e][y] = (e < nlp && y < nuq[e]) ? A.ucol[ent(buq[e], y)] : -2;
+    int cnt = 0, out = pass ? A.xptr[p] : 0;
+#pragma unroll
+    for (int e = 0; e < SE; e++) {
+        if (e >= nlp) break;
+#pragma unroll
+        for (int e2 = e + 1; e2 <= SE; e2++) {
+            if (e2 > nlp + nup) break;
+            int y = -1;
+#pragma unroll
+            for (int yy = SE - 1; yy >= 0; yy--)
+                if (u[e][yy] == c[e2]) y = yy;
+            if (y < 0) continue;
+            long ky = ent(buq[e], y);
+            if (e2 == nlp) {
+                if (pass == 0) A.ldiag[ent(bl, e)] = (int)ky;
+            } else {
+                if (pass) A.xl[out + cnt] = make_int4(e, e2, (int)ky, 0);
+                cnt++;
             }
         }
     }
