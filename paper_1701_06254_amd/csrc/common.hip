@@ -169,23 +169,40 @@ __global__ __launch_bounds__(RS_BS) void k_rs_hist(const unsigned *key, int n, i
     hist[(long)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one pass.  Every element's stable rank among the equal digits
+// of its tile comes from wavefront ballots, carried across the tile's
+// rounds in LDS; the tile is then placed in LDS in digit order and written
+// out from there, so each digit's run of the tile leaves as consecutive
+// addresses instead of one element per digit per round.
 __global__ __launch_bounds__(RS_BS) void k_rs_scatter(const unsigned *key, const unsigned *val,
                                                       int n, int shift, int ntiles,
                                                       const int *off, unsigned *okey,
                                                       unsigned *oval) {
     __shared__ int run[256];
     __shared__ int wc[RS_BS / 64][256];
+    __shared__ int toff[256], goff[256];
+    __shared__ unsigned sk[RS_TILE], sv[RS_TILE];
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     run[threadIdx.x] = 0;
+    goff[threadIdx.x] = off[(long)threadIdx.x * ntiles + blockIdx.x];
     long base = (long)blockIdx.x * RS_TILE;
+    int cnt = (int)min((long)RS_TILE, (long)n - base);
     unsigned long long lt = (1ull << lane) - 1ull;
+    unsigned kr[RS_ROUNDS], vr[RS_ROUNDS];
+    int rk[RS_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; r++) {
+        int j = r * RS_BS + threadIdx.x;
+        bool valid = j < cnt;
+        kr[r] = valid ? key[base + j] : 0u;
+        vr[r] = valid ? val[base + j] : 0u;
+    }
+#pragma unroll
     for (int r = 0; r < RS_ROUNDS; r++) {
         for (int w = 0; w < RS_BS / 64; w++) wc[w][threadIdx.x] = 0;
         __syncthreads();
-        long i = base + (long)r * RS_BS + threadIdx.x;
-        bool valid = i < n;
-        unsigned k = valid ? key[i] : 0u, v = valid ? val[i] : 0u;
-        unsigned d = (k >> shift) & 255u;
+        bool valid = r * RS_BS + (int)threadIdx.x < cnt;
+        unsigned d = (kr[r] >> shift) & 255u;
         unsigned long long peers = __ballot(valid);
         for (int b = 0; b < 8; b++) {
             unsigned long long bb = __ballot(valid && ((d >> b) & 1u));
@@ -194,18 +211,46 @@ __global__ __launch_bounds__(RS_BS) void k_rs_scatter(const unsigned *key, const
         int rank_w = __popcll(peers & lt);
         if (valid && rank_w == 0) wc[wid][d] = __popcll(peers);
         __syncthreads();
-        if (valid) {
-            int before = 0;
-            for (int w = 0; w < wid; w++) before += wc[w][d];
-            long pos = (long)off[(long)d * ntiles + blockIdx.x] + run[d] + before + rank_w;
-            okey[pos] = k;
-            oval[pos] = v;
-        }
+        int before = 0;
+        for (int w = 0; w < wid; w++) before += wc[w][d];
+        rk[r] = run[d] + before + rank_w;
         __syncthreads();
         int add = 0;
         for (int w = 0; w < RS_BS / 64; w++) add += wc[w][threadIdx.x];
         run[threadIdx.x] += add;
-        __syncthreads();
+    }
+    __syncthreads();
+    // exclusive scan of the tile's digit counts (one wavefront)
+    if (wid == 0) {
+        int c0 = run[4 * lane], c1 = run[4 * lane + 1], c2 = run[4 * lane + 2],
+            c3 = run[4 * lane + 3];
+        int sum = c0 + c1 + c2 + c3, inc = sum;
+        for (int o = 1; o < 64; o <<= 1) {
+            int t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        int ex = inc - sum;
+        toff[4 * lane] = ex;
+        toff[4 * lane + 1] = ex + c0;
+        toff[4 * lane + 2] = ex + c0 + c1;
+        toff[4 * lane + 3] = ex + c0 + c1 + c2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RS_ROUNDS; r++) {
+        if (r * RS_BS + (int)threadIdx.x < cnt) {
+            int q = toff[(kr[r] >> shift) & 255u] + rk[r];
+            sk[q] = kr[r];
+            sv[q] = vr[r];
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += RS_BS) {
+        unsigned k = sk[j];
+        unsigned d = (k >> shift) & 255u;
+        long pos = (long)goff[d] + (j - toff[d]);
+        okey[pos] = k;
+        oval[pos] = sv[j];
     }
 }
 
