@@ -41,10 +41,20 @@ constexpr int MDOT_BLOCKS = 1024;       // workgroups of the multi-dot (grid-str
 // does not depend on scheduling.  (A last-workgroup ticket in one launch
 // would need a device-scope fence in every workgroup, which on this GPU
 // writes back and invalidates the L2.)
-template <int NV>
-__global__ __launch_bounds__(BS) void k_mdot(const double *V, long ld, int nv, const double *w,
-                                             long N, double *part) {
+//
+// With UPD the launch first applies a Gram-Schmidt pass, w <- w - V h (h
+// from the previous multi-dot), row by row in the same order as k_mupdate,
+// and takes the products from the updated rows: the reorthogonalising pass
+// and the next projection share one read of the basis.
+template <int NV, bool UPD>
+__global__ __launch_bounds__(BS) void k_mdot(const double *V, long ld, int nv, const double *hin,
+                                             double *w, long N, double *part) {
     __shared__ double red[BS / 64][MAXV];
+    __shared__ double hs[UPD ? MAXV : 1];
+    if (UPD) {
+        for (int k = threadIdx.x; k < nv; k += BS) hs[k] = hin[k];
+        __syncthreads();
+    }
     double acc[NV + 1];
 #pragma unroll
     for (int k = 0; k <= NV; k++) acc[k] = 0.0;
@@ -62,6 +72,18 @@ __global__ __launch_bounds__(BS) void k_mdot(const double *V, long ld, int nv, c
             const double *vk = k < nv ? V + (long)k * ld : vl;
             a[k] = vk[i0];
             b[k] = two ? vk[i1] : 0.0;
+        }
+        if (UPD) {
+#pragma unroll
+            for (int k = 0; k < NV; k++) {
+                if (k < nv) {
+                    w0 -= hs[k] * a[k];
+                    w1 -= hs[k] * b[k];
+                }
+            }
+            w[i0] = w0;
+            if (two) w[i1] = w1;
+            else w1 = 0.0;
         }
 #pragma unroll
         for (int k = 0; k < NV; k++) acc[k] += a[k] * w0 + b[k] * w1;
@@ -186,11 +208,17 @@ struct Krylov {
 
 static Krylov &krylov_for(r2p_cpr *P);
 
-static int mdot(Krylov &K, const double *V, int nv, const double *w, long N, hipStream_t s,
-                double *hhost) {
+// h = V^T w and w.w into K.h (and hhost); with upd (= K.h of the previous
+// projection) w first loses V upd in the same launch.
+static int mdot(Krylov &K, const double *V, int nv, double *w, long N, hipStream_t s,
+                double *hhost, const double *upd = nullptr) {
     int nb = std::max(1, std::min(MDOT_BLOCKS, r2p_blocks(N, 2 * BS)));
     R2P_TRY(K.part.ensure((size_t)nb * MAXV));
-#define R2P_MDOT(NVB) k_mdot<NVB><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p)
+#define R2P_MDOT(NVB)                                                               \
+    do {                                                                            \
+        if (upd) k_mdot<NVB, true><<<nb, BS, 0, s>>>(V, N, nv, upd, w, N, K.part.p); \
+        else k_mdot<NVB, false><<<nb, BS, 0, s>>>(V, N, nv, nullptr, w, N, K.part.p); \
+    } while (0)
     if (nv <= 4) R2P_MDOT(4);
     else if (nv <= 8) R2P_MDOT(8);
     else if (nv <= 12) R2P_MDOT(12);
@@ -517,10 +545,8 @@ extern "C" int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y
                 } else {
                     // second Gram-Schmidt pass
                     inf.reorth++;
-                    k_mupdate<<<nblk, BS, 0, s>>>(K.V.p, N, j + 1, K.h.p, w, N, 1.0, w);
-                    R2P_LAUNCH();
                     double h2[MAXV];
-                    R2P_TRY(mdot(K, K.V.p, j + 1, w, N, s, h2));
+                    R2P_TRY(mdot(K, K.V.p, j + 1, w, N, s, h2, K.h.p));
                     double hs2 = 0.0;
                     for (int i = 0; i <= j; i++) { hh[i] += h2[i]; hs2 += h2[i] * h2[i]; }
                     double wn = h2[j + 1] - hs2;
