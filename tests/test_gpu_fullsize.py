@@ -172,3 +172,21 @@ def test_fullsize_newton_step(big):
     assert nrm <= 1.01e-8
     sw = x1[1:2 * mo.n:2]
     assert np.all(np.isfinite(x1)) and sw.min() >= -1e-12 and sw.max() <= 1 + 1e-12
+
+
+def test_amg_setup_error_reaches_caller(big):
+    """The AMG set-up runs on a worker thread and its own stream beside the
+    RAS set-up.  An error raised there (a one-level hierarchy leaves a 2M-row
+    coarsest matrix, above the dense limit) reaches the caller with its
+    message, and the same handle then sets up and solves normally."""
+    dev, w, x0 = big["dev"], big["w"], big["x0"]
+    mg = dev.Model(w)
+    J = dev.Jacobian(mg)
+    J.assemble(_t(x0), _t(x0), DT)
+    P = dev.Cpr()
+    with pytest.raises(dev.R2PError, match="coarsest AMG level too large"):
+        P.setup(J, dev.cpr_opts(max_levels=1))
+    b = J.assemble(_t(x0), _t(x0), DT)
+    P.setup(J, dev.cpr_opts())
+    _, info = dev.solve(J, P, b)
+    assert info.status == 0 and info.relres <= 1e-8
