@@ -363,6 +363,8 @@ __global__ __launch_bounds__(1024) void k_dense_lu_inv(int n, double *a, int *pi
 }
 
 // --------------------------------------------------------------- set-up
+// Everything runs in order on one stream; the host waits only where it
+// needs a count (the scans that return totals) and for the final status.
 // Member lists (CSR, ascending) of the nc aggregates of agg[0..n).
 static int build_members(r2p_cpr *P, int n, const int *agg, int nc, DBuf<int> &mptr,
                          DBuf<int> &mem, hipStream_t s) {
@@ -381,7 +383,6 @@ static int build_members(r2p_cpr *P, int n, const int *agg, int nc, DBuf<int> &m
                            P->apin, s));
     k_member_ptr<<<r2p_blocks(n, BS), BS, 0, s>>>(n, nc, key.p, mptr.p);
     R2P_LAUNCH();
-    R2P_HIP(hipStreamSynchronize(s));
     return 0;
 }
 
@@ -428,7 +429,6 @@ static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, c
     k_gal_sum<<<r2p_blocks(nnz_c, BS), BS, 0, s>>>(nnz_c, start.p, idx.p, kt.p, val, colc.p,
                                                    valc.p);
     R2P_LAUNCH();
-    R2P_HIP(hipStreamSynchronize(s));
     *nnzc = nnz_c;
     return 0;
 }
@@ -463,7 +463,6 @@ static int aggregate_pass(r2p_cpr *P, int n, const int *rp, const int *col, cons
     R2P_TRY(agg.ensure(n));
     k_number<<<nb, BS, 0, s>>>(n, match.p, jt.p, flag.p, agg.p);
     R2P_LAUNCH();
-    R2P_HIP(hipStreamSynchronize(s));
     *nc = cnt;
     return 0;
 }
@@ -480,7 +479,6 @@ static int long_rows(r2p_cpr *P, int n, const int *ptr, int thr, DBuf<int> &list
     R2P_TRY(list.ensure(cnt));
     k_long_list<<<r2p_blocks(n, BS), BS, 0, s>>>(n, ptr, thr, flag.p, list.p);
     R2P_LAUNCH();
-    R2P_HIP(hipStreamSynchronize(s));
     *count = cnt;
     return 0;
 }
@@ -543,7 +541,6 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
             cnnz = nnzc;
             k_compose<<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, a.p, A.agg.p);
             R2P_LAUNCH();
-            R2P_HIP(hipStreamSynchronize(s));
             rp = orp.p; col = ocol.p; val = oval.p;
             cn = nc;
         }
