@@ -255,14 +255,23 @@ __global__ void k_gal_runs(int m, int nc, const unsigned *keyI, const unsigned *
 }
 
 // One thread per coarse entry: its terms summed in sorted order (ascending
-// fine row, then stored column).
+// fine row, then stored column), four terms' loads in flight at a time.
 __global__ void k_gal_sum(int nnzc, const int *start, const unsigned *idx, const unsigned *keyJ,
                           const double *val, int *colc, double *valc) {
     int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= nnzc) return;
     int a = start[u], b = start[u + 1];
     double s = 0.0;
-    for (int t = a; t < b; t++) s += val[idx[t]];
+    int t = a;
+    for (; t + 4 <= b; t += 4) {
+        unsigned i0 = idx[t], i1 = idx[t + 1], i2 = idx[t + 2], i3 = idx[t + 3];
+        double v0 = val[i0], v1 = val[i1], v2 = val[i2], v3 = val[i3];
+        s += v0;
+        s += v1;
+        s += v2;
+        s += v3;
+    }
+    for (; t < b; t++) s += val[idx[t]];
     colc[u] = (int)keyJ[a];
     valc[u] = s;
 }
