@@ -350,23 +350,38 @@ __global__ __launch_bounds__(1024) void k_dense_lu_inv(int n, double *a, int *pi
         }
         __syncthreads();
     }
-    // inverse: column c of A^-1 solves A x = e_c
+    // inverse: column c of A^-1 solves A x = e_c, one thread per column.
+    // While they are solved the columns sit interleaved, x_c[i] at
+    // invT[i*n + c], so a wavefront's accesses are contiguous; the matrix is
+    // then transposed in place to invT[c*n + i].
     for (int c = tid; c < n; c += nt) {
-        double *x = invT + (long)c * n;
-        for (int i = 0; i < n; i++) x[i] = i == c ? 1.0 : 0.0;
+        for (int i = 0; i < n; i++) invT[(long)i * n + c] = i == c ? 1.0 : 0.0;
         for (int k = 0; k < n; k++) {
             int p = piv[k];
-            if (p != k) { double t = x[k]; x[k] = x[p]; x[p] = t; }
+            if (p != k) {
+                double t = invT[(long)k * n + c];
+                invT[(long)k * n + c] = invT[(long)p * n + c];
+                invT[(long)p * n + c] = t;
+            }
         }
         for (int i = 0; i < n; i++) {
-            double s = x[i];
-            for (int j = 0; j < i; j++) s -= a[(long)i * n + j] * x[j];
-            x[i] = s;
+            double s = invT[(long)i * n + c];
+            for (int j = 0; j < i; j++) s -= a[(long)i * n + j] * invT[(long)j * n + c];
+            invT[(long)i * n + c] = s;
         }
         for (int i = n - 1; i >= 0; i--) {
-            double s = x[i];
-            for (int j = i + 1; j < n; j++) s -= a[(long)i * n + j] * x[j];
-            x[i] = s / a[(long)i * n + i];
+            double s = invT[(long)i * n + c];
+            for (int j = i + 1; j < n; j++) s -= a[(long)i * n + j] * invT[(long)j * n + c];
+            invT[(long)i * n + c] = s / a[(long)i * n + i];
+        }
+    }
+    __syncthreads();
+    for (long t = tid; t < (long)n * n; t += nt) {
+        int i = (int)(t / n), j = (int)(t % n);
+        if (i < j) {
+            double u = invT[(long)i * n + j];
+            invT[(long)i * n + j] = invT[(long)j * n + i];
+            invT[(long)j * n + i] = u;
         }
     }
 }
