@@ -62,14 +62,15 @@ class CprOpts(C.Structure):
     _fields_ = [("decouple", C.c_int), ("order", C.c_int), ("form", C.c_int),
                 ("px", C.c_int), ("py", C.c_int), ("overlap", C.c_int),
                 ("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int),
-                ("match_rounds", C.c_int), ("agg_passes", C.c_int), ("exact_stages", C.c_int)]
+                ("match_rounds", C.c_int), ("agg_passes", C.c_int), ("kcycle", C.c_int),
+                ("exact_stages", C.c_int)]
 
 
 def cpr_opts(decouple=DEC_QI, order=ORD_POTENTIAL, form=CPR_TWO_STAGE, px=4, py=4, overlap=1,
-             theta=0.25, max_coarse=500, max_levels=20, match_rounds=4, agg_passes=2,
+             theta=0.25, max_coarse=500, max_levels=20, match_rounds=4, agg_passes=2, kcycle=2,
              exact_stages=0):
     return CprOpts(decouple, order, form, px, py, overlap, theta, max_coarse, max_levels,
-                   match_rounds, agg_passes, exact_stages)
+                   match_rounds, agg_passes, kcycle, exact_stages)
 
 
 def lib():
@@ -102,6 +103,8 @@ def lib():
     L.om_dense_lu.argtypes = [C.c_int, f64p, i32p]
     L.om_dense_lu_solve.argtypes = [C.c_int, f64p, i32p, f64p]
     L.om_strength_match.argtypes = [C.POINTER(Csr), C.c_double, C.c_int, i32p]
+    L.om_coupling_weights.argtypes = [C.POINTER(Csr), f64p, f64p]
+    L.om_join_targets.argtypes = [C.POINTER(Csr), C.c_double, i32p, i32p]
     L.om_galerkin.argtypes = [C.POINTER(Csr), i32p, C.c_int, C.POINTER(Csr)]
     L.om_aggregate.argtypes = [C.POINTER(Csr), C.c_double, C.c_int, i32p]
     L.om_csr_free.argtypes = [C.POINTER(Csr)]
@@ -119,7 +122,7 @@ def lib():
     L.om_api_ras_copy_sub.argtypes = [vp, C.c_int, i32p, u8p, i32p, i32p, f64p, f64p]
     L.om_api_ras_apply.argtypes = [vp, f64p, f64p]
     L.om_api_amg_create.argtypes = [C.POINTER(Csr), C.c_double, C.c_int, C.c_int, C.c_int,
-                                    C.c_int, C.POINTER(C.c_int)]
+                                    C.c_int, C.c_int, C.POINTER(C.c_int)]
     L.om_api_amg_create.restype = vp
     L.om_api_amg_destroy.argtypes = [vp]
     L.om_api_amg_h_nlev.argtypes = [vp]
@@ -132,7 +135,8 @@ def lib():
                               C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.om_newton_step.argtypes = [vp, f64p, C.c_double, C.POINTER(CprOpts), C.c_int, C.c_double,
                                  C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double,
-                                 C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), f64p]
+                                 C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), f64p, f64p,
+                                 f64p, f64p]
     _lib = L
     return L
 
@@ -285,18 +289,27 @@ class Model:
         return ph
 
     def newton_step(self, x, dt, opts=None, restart=30, rtol=1e-8, maxit=300, ntol=1e-8,
-                    max_newton=20, exact_linear=False, forcing=0, ds_max=0.2, krylov=0):
-        """One implicit step in place; returns (status, newton_its, linear_its, hist)."""
+                    max_newton=20, exact_linear=False, forcing=0, ds_max=0.2, krylov=0,
+                    norms=False):
+        """One implicit step in place; returns (status, newton_its, linear_its, hist), and
+        with norms=True also a dict of per-iteration ||F||_2, ||b - J y||_2 and the
+        linear tolerance used."""
         opts = cpr_opts() if opts is None else opts
         xx = _f64(x).copy()
         ni, li = C.c_int(), C.c_int()
         hist = np.zeros(max_newton + 1)
+        fn, rn, eta = (np.full(max_newton + 1, np.nan) for _ in range(3))
         rc = lib().om_newton_step(self.h, xx, float(dt), C.byref(opts), restart, rtol, maxit,
                                   ntol, max_newton, int(exact_linear), int(forcing),
-                                  float(ds_max), int(krylov), C.byref(ni), C.byref(li), hist)
+                                  float(ds_max), int(krylov), C.byref(ni), C.byref(li), hist,
+                                  fn, rn, eta)
         if rc == 0:
             x[:] = xx
-        return rc, ni.value, li.value, hist[:ni.value + 1]
+        out = (rc, ni.value, li.value, hist[:ni.value + 1])
+        if norms:
+            k = ni.value
+            return out + (dict(fnorm=fn[:k], rnorm=rn[:k], eta=eta[:k]),)
+        return out
 
 
 def potential_order(phi, cells=None):
@@ -386,11 +399,15 @@ def galerkin(A, agg, nc):
 class Amg:
     """Standalone AMG hierarchy on a scalar CSR matrix."""
 
-    def __init__(self, A, theta=0.25, max_coarse=500, max_levels=20, rounds=4, passes=2):
+    def __init__(self, A, theta=0.25, max_coarse=500, max_levels=20, rounds=4, passes=2,
+                 kcycle=2):
         rc = C.c_int()
         self._A = A.cstruct()
         self.h = lib().om_api_amg_create(C.byref(self._A), theta, max_coarse, max_levels,
-                                         rounds, passes, C.byref(rc))
+                                         rounds, passes, kcycle, C.byref(rc))
+        self.rc = rc.value
+        if rc.value == 1:
+            raise ValueError("AMG coarsening stalled above the dense coarsest size")
         if rc.value:
             raise ValueError("coarsest matrix singular")
 

@@ -7,22 +7,33 @@
  * oracle uses the reading adopted for both sides:
  *   - A_pp = the (pressure-equation, pressure) entry of every decoupled
  *     cell-cell block, restriction Pi_r of Eq 34 applied to rows and columns;
- *   - strength: j is a strong neighbour of i when -a_ij > 0 and
- *     -a_ij >= theta * max_{k != i} (-a_ik);
+ *   - coupling weight of rows i != j: w_ij = -(a_ij + a_ji) / 2 (a missing
+ *     entry counts as 0), the same number seen from either row; M_i = the
+ *     largest w_ik of row i (0 when none is positive); the pair is strong
+ *     when w_ij > 0 and w_ij >= theta * M_i or w_ij >= theta * M_j, a
+ *     relation that is symmetric too;
  *   - pairwise matching by handshakes: in each round every unmatched row
- *     proposes its strongest unmatched strong neighbour (largest -a_ij,
- *     ties to the smaller index); mutual proposals become pairs; rows left
- *     after the last round join the pair of their strongest strong
- *     neighbour that is in a pair (ties to the smaller index), or stay
- *     singletons when there is none;
+ *     proposes its strongest unmatched strong neighbour (largest w_ij, ties
+ *     to the smaller index); mutual proposals become pairs.  Because weight,
+ *     relation and tie rule are symmetric, a chain of proposals climbs to a
+ *     mutual pair, so every round pairs off at least one row of every group
+ *     of unmatched rows joined by strong couplings.  Rows left after the last
+ *     round join the pair of their strongest strong neighbour that is in a
+ *     pair (same order), or stay singletons when there is none;
  *   - `passes` aggregation passes per level (each on the Galerkin product of
  *     the previous one); aggregates are numbered by their leader (the
  *     smaller row of a pair, or the singleton);
  *   - piecewise-constant prolongation P, Galerkin coarse matrix A_c = P^T A P
  *     summed in ascending fine row, then stored column order;
  *   - l1-Jacobi smoothing (d_i = sum_j |a_ij|), one sweep before and after
- *     the coarse correction, zero initial guess, V-cycle;
- *   - coarsest level solved by dense LU with partial pivoting.
+ *     the coarse correction, zero initial guess;
+ *   - the cycle: on the `kcycle` finest levels the coarse system is solved by
+ *     two steps of the generalised conjugate residual method, each
+ *     preconditioned by one cycle on the coarser level (a K-cycle); below,
+ *     one cycle (a V-cycle);
+ *   - coarsest level solved by dense LU with partial pivoting.  Coarsening
+ *     stops when a level makes no progress; a coarsest level above 4096
+ *     rows is then reported as a soft failure of the set-up.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -53,18 +64,44 @@ void om_extract_pressure(const om_bsr *A, int ncell, om_csr *P)
     }
 }
 
+/* a_ij, or 0 when row i stores no column j. */
+static double entry(const om_csr *A, int i, int j)
+{
+    for (int z = A->rp[i]; z < A->rp[i + 1]; z++)
+        if (A->col[z] == j) return A->val[z];
+    return 0.0;
+}
+
+/* w[z] = -(a_ij + a_ji)/2 for each stored off-diagonal entry z = (i, j)
+ * (0 on the diagonal), and M_i = max(0, max_j w_ij). */
+void om_coupling_weights(const om_csr *A, double *w, double *M)
+{
+    for (int i = 0; i < A->n; i++) {
+        double mx = 0.0;
+        for (int z = A->rp[i]; z < A->rp[i + 1]; z++) {
+            int j = A->col[z];
+            w[z] = 0.0;
+            if (j == i) continue;
+            w[z] = -(A->val[z] + entry(A, j, i)) / 2.0;
+            if (w[z] > mx) mx = w[z];
+        }
+        M[i] = mx;
+    }
+}
+
+static int strong(double wij, double Mi, double Mj, double theta)
+{
+    return wij > 0.0 && (wij >= theta * Mi || wij >= theta * Mj);
+}
+
 void om_strength_match(const om_csr *A, double theta, int rounds, int *match)
 {
     int n = A->n;
     int *prop = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
-    double *thr = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
-    for (int i = 0; i < n; i++) {
-        double mx = 0.0;
-        for (int z = A->rp[i]; z < A->rp[i + 1]; z++)
-            if (A->col[z] != i && -A->val[z] > mx) mx = -A->val[z];
-        thr[i] = theta * mx;
-        match[i] = -1;
-    }
+    double *w = (double *)malloc(sizeof(double) * (A->nnz > 0 ? A->nnz : 1));
+    double *M = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    om_coupling_weights(A, w, M);
+    for (int i = 0; i < n; i++) match[i] = -1;
     for (int r = 0; r < rounds; r++) {
         for (int i = 0; i < n; i++) {
             prop[i] = -1;
@@ -72,9 +109,9 @@ void om_strength_match(const om_csr *A, double theta, int rounds, int *match)
             double best = 0.0;
             for (int z = A->rp[i]; z < A->rp[i + 1]; z++) {
                 int j = A->col[z];
-                double s = -A->val[z];
-                if (j == i || match[j] >= 0 || !(s > 0.0) || s < thr[i]) continue;
-                if (s > best) { best = s; prop[i] = j; }
+                if (j == i || match[j] >= 0 || !strong(w[z], M[i], M[j], theta)) continue;
+                /* columns ascend, so a strict > keeps the smaller index on ties */
+                if (prop[i] < 0 || w[z] > best) { best = w[z]; prop[i] = j; }
             }
         }
         for (int i = 0; i < n; i++) {
@@ -82,7 +119,7 @@ void om_strength_match(const om_csr *A, double theta, int rounds, int *match)
             if (match[i] < 0 && j >= 0 && prop[j] == i) match[i] = j;
         }
     }
-    free(prop); free(thr);
+    free(prop); free(w); free(M);
 }
 
 /* Rows left unmatched after the handshake rounds join the pair of their
@@ -91,93 +128,48 @@ void om_strength_match(const om_csr *A, double theta, int rounds, int *match)
  * or -1. */
 void om_join_targets(const om_csr *A, double theta, const int *match, int *jt)
 {
-    for (int i = 0; i < A->n; i++) {
-        double mx = 0.0;
-        for (int z = A->rp[i]; z < A->rp[i + 1]; z++)
-            if (A->col[z] != i && -A->val[z] > mx) mx = -A->val[z];
-        double thr = theta * mx;
+    int n = A->n;
+    double *w = (double *)malloc(sizeof(double) * (A->nnz > 0 ? A->nnz : 1));
+    double *M = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    om_coupling_weights(A, w, M);
+    for (int i = 0; i < n; i++) {
         jt[i] = -1;
         if (match[i] >= 0) continue;
         double best = 0.0;
         for (int z = A->rp[i]; z < A->rp[i + 1]; z++) {
             int j = A->col[z];
-            double s = -A->val[z];
-            if (j == i || match[j] < 0 || !(s > 0.0) || s < thr) continue;
-            if (s > best) { best = s; jt[i] = j; }
+            if (j == i || match[j] < 0 || !strong(w[z], M[i], M[j], theta)) continue;
+            if (jt[i] < 0 || w[z] > best) { best = w[z]; jt[i] = j; }
         }
     }
+    free(w); free(M);
 }
 
-/* Aggregates of one pass: pairs, the rows that join them, and the remaining
- * singletons, numbered by their leader (the smaller row of the pair, or the
- * singleton).  Joining is bounded: in each of `join_rounds` rounds every row
- * still alone proposes to the pair of its strongest strong neighbour that
- * belongs to a pair, and each pair takes only its strongest proposer (the
- * proposer's coupling rounded to single precision, ties to the smaller
- * row), so an aggregate holds at most 2 + join_rounds rows.  With
- * join_rounds < 0 every proposer joins (unbounded). */
-int om_aggregate_bounded(const om_csr *A, double theta, int rounds, int join_rounds, int *agg)
+/* Aggregates of one pass: pairs, the rows that join them and the remaining
+ * singletons, numbered in order of their leader (the smaller row of the
+ * pair, or the singleton).  Returns the number of aggregates. */
+int om_aggregate(const om_csr *A, double theta, int rounds, int *agg)
 {
     int n = A->n;
     int *match = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
     int *jt = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
-    int *lead = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));   /* pair leader or -1 */
-    unsigned long long *best = (unsigned long long *)malloc(sizeof(unsigned long long) * (n > 0 ? n : 1));
+    int *lead = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
     om_strength_match(A, theta, rounds, match);
-    for (int i = 0; i < n; i++) lead[i] = match[i] >= 0 ? (i < match[i] ? i : match[i]) : -1;
-    if (join_rounds < 0) {
-        om_join_targets(A, theta, match, jt);
-        for (int i = 0; i < n; i++)
-            if (match[i] < 0 && jt[i] >= 0) lead[i] = -2 - lead[jt[i]];   /* joined, mark */
-        for (int i = 0; i < n; i++)
-            if (lead[i] <= -2) lead[i] = -2 - lead[i];
-    }
-    for (int r = 0; r < join_rounds; r++) {
-        /* proposals: strongest strong neighbour that is in a pair aggregate */
-        for (int i = 0; i < n; i++) best[i] = 0ull;
-        for (int i = 0; i < n; i++) {
-            jt[i] = -1;
-            if (lead[i] >= 0) continue;
-            double mx = 0.0;
-            for (int z = A->rp[i]; z < A->rp[i + 1]; z++)
-                if (A->col[z] != i && -A->val[z] > mx) mx = -A->val[z];
-            double thr = theta * mx, bs = 0.0;
-            for (int z = A->rp[i]; z < A->rp[i + 1]; z++) {
-                int j = A->col[z];
-                double s = -A->val[z];
-                if (j == i || lead[j] < 0 || !(s > 0.0) || s < thr) continue;
-                if (s > bs) { bs = s; jt[i] = j; }
-            }
-            if (jt[i] >= 0) {
-                float f = (float)bs;
-                unsigned int fb;
-                memcpy(&fb, &f, sizeof(fb));
-                unsigned long long key = ((unsigned long long)fb << 32) | (0xFFFFFFFFull - (unsigned)i);
-                int L = lead[jt[i]];
-                if (key > best[L]) best[L] = key;
-            }
-        }
-        /* acceptance: the pair keeps its strongest proposer */
-        for (int i = 0; i < n; i++) {
-            if (jt[i] < 0) continue;
-            int L = lead[jt[i]];
-            if ((unsigned)(0xFFFFFFFFull - (best[L] & 0xFFFFFFFFull)) == (unsigned)i) lead[i] = -2 - L;
-        }
-        for (int i = 0; i < n; i++)
-            if (lead[i] <= -2) lead[i] = -2 - lead[i];
+    om_join_targets(A, theta, match, jt);
+    for (int i = 0; i < n; i++) {
+        if (match[i] >= 0) lead[i] = i < match[i] ? i : match[i];
+        else if (jt[i] >= 0) {
+            int k = jt[i];
+            lead[i] = k < match[k] ? k : match[k];
+        } else lead[i] = i;
     }
     int nc = 0;
     for (int i = 0; i < n; i++)
-        if ((match[i] >= 0 && i < match[i]) || lead[i] < 0) agg[i] = nc++;
+        if (lead[i] == i) agg[i] = nc++;
     for (int i = 0; i < n; i++)
-        if (lead[i] >= 0 && lead[i] != i) agg[i] = agg[lead[i]];
-    free(match); free(jt); free(lead); free(best);
+        if (lead[i] != i) agg[i] = agg[lead[i]];
+    free(match); free(jt); free(lead);
     return nc;
-}
-
-int om_aggregate(const om_csr *A, double theta, int rounds, int *agg)
-{
-    return om_aggregate_bounded(A, theta, rounds, -1, agg);
 }
 
 static int cmp_int(const void *a, const void *b)
@@ -238,8 +230,10 @@ static void csr_copy(om_csr *d, const om_csr *s)
     memcpy(d->val, s->val, sizeof(double) * s->nnz);
 }
 
+static double *vec(int n) { return (double *)malloc(sizeof(double) * (n > 0 ? n : 1)); }
+
 int om_amg_setup(om_amg *H, const om_csr *A0, double theta, int max_coarse, int max_levels,
-                 int rounds, int passes)
+                 int rounds, int passes, int kcycle)
 {
     memset(H, 0, sizeof(*H));
     if (max_levels > 24) max_levels = 24;
@@ -274,27 +268,38 @@ int om_amg_setup(om_amg *H, const om_csr *A0, double theta, int max_coarse, int 
         l++;
     }
     H->nlev = l + 1;
+    H->kcycle = kcycle;
     for (int k = 0; k < H->nlev; k++) {
         const om_csr *A = &H->A[k];
-        H->l1[k] = (double *)malloc(sizeof(double) * (A->n > 0 ? A->n : 1));
+        H->l1[k] = vec(A->n);
         for (int i = 0; i < A->n; i++) {
             double s = 0.0;
             for (int z = A->rp[i]; z < A->rp[i + 1]; z++) s += fabs(A->val[z]);
             H->l1[k][i] = s;
         }
-        H->wr[k] = (double *)malloc(sizeof(double) * (A->n > 0 ? A->n : 1));
-        H->wx[k] = (double *)malloc(sizeof(double) * (A->n > 0 ? A->n : 1));
-        H->wb[k] = (double *)malloc(sizeof(double) * (A->n > 0 ? A->n : 1));
+        H->wr[k] = vec(A->n);
+        H->wx[k] = vec(A->n);
+        H->wb[k] = vec(A->n);
+        H->kw[k] = vec(5 * A->n);
     }
     const om_csr *C = &H->A[H->nlev - 1];
     int nc = C->n;
     H->ncoarse = nc;
-    if (nc > 4096) return -2;    /* coarsening stalled: no dense solve of that size */
+    if (nc > 4096) return 1;     /* coarsening stalled: no dense solve of that size */
     H->lu = (double *)calloc((size_t)nc * nc > 0 ? (size_t)nc * nc : 1, sizeof(double));
     H->piv = (int *)malloc(sizeof(int) * (nc > 0 ? nc : 1));
     for (int i = 0; i < nc; i++)
         for (int z = C->rp[i]; z < C->rp[i + 1]; z++) H->lu[(size_t)i * nc + C->col[z]] += C->val[z];
-    return om_dense_lu(nc, H->lu, H->piv);
+    return om_dense_lu(nc, H->lu, H->piv) ? 2 : 0;
+}
+
+static void csr_mv(const om_csr *A, const double *x, double *y)
+{
+    for (int i = 0; i < A->n; i++) {
+        double s = 0.0;
+        for (int z = A->rp[i]; z < A->rp[i + 1]; z++) s += A->val[z] * x[A->col[z]];
+        y[i] = s;
+    }
 }
 
 static void csr_resid(const om_csr *A, const double *b, const double *x, double *r)
@@ -306,7 +311,37 @@ static void csr_resid(const om_csr *A, const double *b, const double *x, double 
     }
 }
 
-static void vcycle(const om_amg *H, int l, const double *b, double *x)
+static void cycle(const om_amg *H, int l, const double *b, double *x);
+
+/* Coarse correction at level c by two steps of the generalised conjugate
+ * residual method on A_c x = b, each preconditioned by one cycle at level c:
+ *   p1 = C(b), q1 = A p1, a1 = (q1.b)/(q1.q1), r = b - a1 q1;
+ *   p2 = C(r), q2 = A p2, beta = (q1.q2)/(q1.q1), p2 -= beta p1, q2 -= beta q1,
+ *   a2 = (q2.r)/(q2.q2);  x = a1 p1 + a2 p2.
+ * A zero denominator gives a zero step. */
+static void kstep(const om_amg *H, int c, const double *b, double *x)
+{
+    const om_csr *A = &H->A[c];
+    int n = A->n;
+    double *p1 = H->kw[c], *p2 = p1 + n, *q1 = p2 + n, *q2 = q1 + n, *r = q2 + n;
+    cycle(H, c, b, p1);
+    csr_mv(A, p1, q1);
+    double qq = om_dot(n, q1, q1);
+    double a1 = qq > 0.0 ? om_dot(n, q1, b) / qq : 0.0;
+    for (int i = 0; i < n; i++) r[i] = b[i] - a1 * q1[i];
+    cycle(H, c, r, p2);
+    csr_mv(A, p2, q2);
+    double beta = qq > 0.0 ? om_dot(n, q1, q2) / qq : 0.0;
+    for (int i = 0; i < n; i++) {
+        p2[i] = p2[i] - beta * p1[i];
+        q2[i] = q2[i] - beta * q1[i];
+    }
+    double q22 = om_dot(n, q2, q2);
+    double a2 = q22 > 0.0 ? om_dot(n, q2, r) / q22 : 0.0;
+    for (int i = 0; i < n; i++) x[i] = a1 * p1[i] + a2 * p2[i];
+}
+
+static void cycle(const om_amg *H, int l, const double *b, double *x)
 {
     const om_csr *A = &H->A[l];
     int n = A->n;
@@ -323,7 +358,8 @@ static void vcycle(const om_amg *H, int l, const double *b, double *x)
     double *bc = H->wb[l + 1], *xc = H->wx[l + 1];
     for (int I = 0; I < nc; I++) bc[I] = 0.0;
     for (int i = 0; i < n; i++) bc[H->agg[l][i]] += r[i];       /* restriction P^T r */
-    vcycle(H, l + 1, bc, xc);
+    if (l < H->kcycle && l + 1 < H->nlev - 1) kstep(H, l + 1, bc, xc);
+    else cycle(H, l + 1, bc, xc);
     for (int i = 0; i < n; i++) x[i] += xc[H->agg[l][i]];       /* prolongation P xc */
     csr_resid(A, b, x, r);
     for (int i = 0; i < n; i++) x[i] += r[i] / d[i];             /* post-smooth */
@@ -331,7 +367,7 @@ static void vcycle(const om_amg *H, int l, const double *b, double *x)
 
 void om_amg_vcycle(const om_amg *H, const double *b, double *x)
 {
-    vcycle(H, 0, b, x);
+    cycle(H, 0, b, x);
 }
 
 void om_amg_free(om_amg *H)
@@ -339,6 +375,7 @@ void om_amg_free(om_amg *H)
     for (int k = 0; k < H->nlev; k++) {
         om_csr_free(&H->A[k]);
         free(H->l1[k]); free(H->agg[k]); free(H->wr[k]); free(H->wx[k]); free(H->wb[k]);
+        free(H->kw[k]);
     }
     free(H->lu); free(H->piv);
     memset(H, 0, sizeof(*H));

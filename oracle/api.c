@@ -65,10 +65,10 @@ void om_api_ras_copy_sub(const om_cpr *P, int s, int *glob, unsigned char *owned
 void om_api_ras_apply(const om_cpr *P, const double *r, double *y) { om_ras_apply(&P->ras, r, y); }
 
 om_amg *om_api_amg_create(const om_csr *A, double theta, int max_coarse, int max_levels,
-                          int rounds, int passes, int *rc)
+                          int rounds, int passes, int kcycle, int *rc)
 {
     om_amg *H = (om_amg *)calloc(1, sizeof(om_amg));
-    *rc = om_amg_setup(H, A, theta, max_coarse, max_levels, rounds, passes);
+    *rc = om_amg_setup(H, A, theta, max_coarse, max_levels, rounds, passes, kcycle);
     return H;
 }
 

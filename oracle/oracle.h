@@ -86,6 +86,8 @@ typedef struct {
     double *lu;       /* coarsest dense LU (row-major), with partial pivoting */
     int *piv;
     double *wr[24], *wx[24], *wb[24];
+    double *kw[24];   /* K-cycle work vectors of a level: p1, p2, q1, q2, r */
+    int kcycle;       /* coarse corrections of levels < kcycle are K-cycles */
 } om_amg;
 
 /* ---------------------------------------------------------------- options */
@@ -98,6 +100,7 @@ typedef struct {
     int px, py, overlap;
     double theta;         /* AMG strength threshold */
     int max_coarse, max_levels, match_rounds, agg_passes;
+    int kcycle;           /* AMG levels whose coarse correction is a K-cycle */
     int exact_stages;     /* 1: RAS and V-cycle replaced by dense solves (pin of Alg 2) */
 } om_cpr_opts;
 
@@ -157,16 +160,18 @@ int  om_bilu0(om_bsr *A, double *dinv, int *diag);
 void om_bilu0_solve(const om_bsr *LU, const double *dinv, const int *diag, double *v);
 
 /* amg.c */
+/* Returns 0, 1 when coarsening stalled above the dense coarsest size (soft
+ * failure), or 2 when the coarsest matrix is singular. */
 int  om_amg_setup(om_amg *H, const om_csr *A0, double theta, int max_coarse, int max_levels,
-                  int rounds, int passes);
+                  int rounds, int passes, int kcycle);
 void om_amg_vcycle(const om_amg *H, const double *b, double *x);
 void om_amg_free(om_amg *H);
 void om_extract_pressure(const om_bsr *A, int ncell, om_csr *App);
 void om_strength_match(const om_csr *A, double theta, int rounds, int *match);
 void om_galerkin(const om_csr *A, const int *agg, int nc, om_csr *Ac);
 void om_join_targets(const om_csr *A, double theta, const int *match, int *jt);
+void om_coupling_weights(const om_csr *A, double *w, double *M);
 int  om_aggregate(const om_csr *A, double theta, int rounds, int *agg);
-int  om_aggregate_bounded(const om_csr *A, double theta, int rounds, int join_rounds, int *agg);
 
 /* solver.c */
 int  om_cpr_setup(om_cpr *P, const om_bsr *Adec, const om_model *mdl, const double *x,
@@ -181,7 +186,7 @@ int  om_bicgstab(const om_bsr *A, const om_cpr *P, const double *b, double *x, d
 int  om_newton_step(const om_model *m, double *x, double dt, const om_cpr_opts *o, int restart,
                     double rtol, int maxit, double ntol, int max_newton, int exact_linear,
                     int forcing, double ds_max, int krylov, int *newton_its, int *lin_its,
-                    double *res_hist);
+                    double *res_hist, double *fn_hist, double *rn_hist, double *eta_hist);
 
 #ifdef __cplusplus
 }

@@ -52,7 +52,7 @@ int om_cpr_setup(om_cpr *P, const om_bsr *A, const om_model *mdl, const double *
     } else {
         rc = om_ras_setup(&P->ras, A, mdl, x, o->px, o->py, o->overlap, o->order);
         if (!rc) rc = om_amg_setup(&P->amg, &App, o->theta, o->max_coarse, o->max_levels,
-                                   o->match_rounds, o->agg_passes);
+                                   o->match_rounds, o->agg_passes, o->kcycle);
     }
     om_csr_free(&App);
     return rc;
@@ -285,6 +285,10 @@ done:
 /* One implicit time step x^n -> x^{n+1} by Newton's method (in place).
  * forcing 0: every linear solve to rtol; forcing 1: Eisenstat-Walker
  * (second choice of Eq 26, clipped to [0.01, 0.1], starting at 0.1).
+ * Per Newton iteration l (NULL allowed): fn_hist[l] = ||F(x_l)||_2,
+ * eta_hist[l] = the linear tolerance used, rn_hist[l] = ||b - J y||_2 of the
+ * solve (Eq 27).  A CPR set-up that fails (singular pivot, stalled AMG
+ * coarsening) ends the step as not converged.
  * exact_linear: solve each Newton system by dense LU instead of CPR-Krylov;
  * krylov 0: FGMRES(restart), 1: BiCGSTAB.
  * ds_max > 0 limits each cell's saturation change per Newton iteration.
@@ -293,7 +297,7 @@ done:
 int om_newton_step(const om_model *m, double *x, double dt, const om_cpr_opts *o, int restart,
                    double rtol, int maxit, double ntol, int max_newton, int exact_linear,
                    int forcing, double ds_max, int krylov, int *newton_its, int *lin_its,
-                   double *res_hist)
+                   double *res_hist, double *fn_hist, double *rn_hist, double *eta_hist)
 {
     int n = m->n, N = 2 * (m->n + m->nw);
     double *xo = (double *)malloc(sizeof(double) * N);
@@ -325,6 +329,8 @@ int om_newton_step(const om_model *m, double *x, double dt, const om_cpr_opts *o
             if (eta > 0.1) eta = 0.1;
         }
         double tol = forcing == 1 ? eta : rtol;
+        if (fn_hist) fn_hist[it] = fn;
+        if (eta_hist) eta_hist[it] = tol;
         if (exact_linear) {
             double *D = (double *)malloc(sizeof(double) * (size_t)N * N);
             int *piv = (int *)malloc(sizeof(int) * N);
@@ -341,17 +347,20 @@ int om_newton_step(const om_model *m, double *x, double dt, const om_cpr_opts *o
             om_decouple(&Ad, bd, n, o->decouple);
             om_cpr P;
             int rc = om_cpr_setup(&P, &Ad, m, xk, o);
-            int its = 0; double rr = 0.0;
-            if (!rc) rc = krylov == 1 ? om_bicgstab(&Ad, &P, bd, y, tol, maxit, &its, &rr)
-                                      : om_fgmres(&Ad, &P, bd, y, restart, tol, maxit, &its, &rr, NULL);
+            int its = 0, lrc = 0;
+            double rr = 0.0;
+            if (!rc) lrc = krylov == 1 ? om_bicgstab(&Ad, &P, bd, y, tol, maxit, &its, &rr)
+                                       : om_fgmres(&Ad, &P, bd, y, restart, tol, maxit, &its, &rr, NULL);
             lits += its;
             om_cpr_free(&P);
             om_bsr_free(&Ad);
-            if (rc && forcing == 0) break;
+            if (rc) break;                                        /* set-up failed */
+            if (lrc && forcing == 0) break;
         }
         om_bsr_spmv(&J, y, t);                                    /* r = b - J y, Eq 27 */
         for (int i = 0; i < N; i++) t[i] = b[i] - t[i];
         prev_rn = nrm2(N, t);
+        if (rn_hist) rn_hist[it] = prev_rn;
         prev_fn = fn;
         for (int i = 0; i < N; i++) {                             /* Algorithm 1, update */
             double d = y[i];
