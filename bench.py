@@ -203,6 +203,16 @@ def time_on_stream(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def newton_record(info, dt):
+    """One Newton step's counts and stage times as a plain dict."""
+    r = dict(dt=dt, status=info.status, newton=info.newton_its, linear=info.linear_its,
+             setup_status=info.setup_status)
+    for k in ("ms_assemble", "ms_setup", "ms_decouple", "ms_order", "ms_ras_setup",
+              "ms_amg_setup", "ms_solve", "ms_update", "ms_total"):
+        r[k] = getattr(info, k)
+    return r
+
+
 def run_steps(model, x, dt, nsteps, opts, dt_max, tag, dts=None):
     """nsteps accepted implicit steps on x (in place).  With `dts` given the
     step lengths are replayed instead of controlled.  Returns the next step
@@ -213,10 +223,7 @@ def run_steps(model, x, dt, nsteps, opts, dt_max, tag, dts=None):
             dt = dts[k]
         while True:
             info = model.newton_step(x, dt, opts)
-            recs.append(dict(dt=dt, status=info.status, newton=info.newton_its,
-                             linear=info.linear_its, ms_setup=info.ms_setup,
-                             ms_solve=info.ms_solve, ms_assemble=info.ms_assemble,
-                             ms_total=info.ms_total))
+            recs.append(newton_record(info, dt))
             log(f"{tag} step {k}: dt {dt:.4g} d status {info.status} newton {info.newton_its} "
                 f"linear {info.linear_its} setup {info.ms_setup:.0f} solve {info.ms_solve:.0f} "
                 f"total {info.ms_total:.0f} ms")
@@ -315,10 +322,7 @@ def learned_run(args, model, x0, x64, dts, form, log):
         guess = net.warm_start(model, xl, dt)
         guesses.append(guess)
         info = model.newton_step(xl, dt, o, x_guess=guess)
-        recs.append(dict(dt=dt, status=info.status, newton=info.newton_its,
-                         linear=info.linear_its, ms_setup=info.ms_setup,
-                         ms_solve=info.ms_solve, ms_assemble=info.ms_assemble,
-                         ms_total=info.ms_total, used=info.used_guess))
+        recs.append(dict(newton_record(info, dt), used=info.used_guess))
         log(f"fp32+learned step {k}: dt {dt:.4g} d status {info.status} newton {info.newton_its} "
             f"linear {info.linear_its} guess {info.used_guess} total {info.ms_total:.0f} ms")
         if info.status != 0:
@@ -467,10 +471,7 @@ def large_run(args, w, log):
         guess = net.warm_start(model, xl, dtk)
         info = model.newton_step(xl, dtk, o32, x_guess=guess)
         del guess
-        recsl.append(dict(dt=dtk, status=info.status, newton=info.newton_its,
-                          linear=info.linear_its, ms_setup=info.ms_setup, ms_solve=info.ms_solve,
-                          ms_assemble=info.ms_assemble, ms_total=info.ms_total,
-                          used=info.used_guess))
+        recsl.append(dict(newton_record(info, dtk), used=info.used_guess))
         log(f"fp32+learned step {k}: dt {dtk:.4g} d status {info.status} newton "
             f"{info.newton_its} linear {info.linear_its} guess {info.used_guess} "
             f"total {info.ms_total:.0f} ms")
@@ -499,6 +500,58 @@ def large_run(args, w, log):
     return out
 
 
+def stage_summary(recs):
+    """Per-step means of the Newton step's stage times (ms), the columns of
+    the paper's timing table (Table 5)."""
+    keys = ["ms_assemble", "ms_setup", "ms_decouple", "ms_order", "ms_ras_setup",
+            "ms_amg_setup", "ms_solve", "ms_update", "ms_total"]
+    ok = [r for r in recs if r["status"] == 0] or recs
+    return {k: round(sum(r[k] for r in ok) / max(len(ok), 1), 3) for k in keys}
+
+
+def snapshot_solves(model, states, dt, form, log):
+    """Fixed-snapshot solves: for each named state, the first Newton system of
+    a step of length dt (J(x, x, dt)), CPR set-up and one CPR-FGMRES(30)
+    solve to 1e-8, in FP64 and with the FP32 preconditioner."""
+    import torch
+    from paper_1701_06254_amd import r2p
+    out = []
+    for name, x in states:
+        row = {"state": name, "dt_days": dt}
+        for tag, prec in (("fp64", r2p.FP64), ("fp32", r2p.FP32)):
+            J = r2p.Jacobian(model)
+            b = J.assemble(x, x, dt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P = r2p.Cpr().setup(J, r2p.cpr_opts(form=form, precision=prec))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = r2p.solve(J, P, b)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            row[tag] = {"setup_ms": round((t1 - t0) * 1e3, 2), "solve_ms": round((t2 - t1) * 1e3, 2),
+                        "iterations": info.iterations, "relres": info.relres,
+                        "status": info.status}
+            del P, J
+        log(f"snapshot {name} dt {dt}: {row}")
+        out.append(row)
+    return out
+
+
+def host_cpu():
+    """CPU model name and logical CPU count of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -517,18 +570,21 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the method variants on the last system and the EW-forcing replay")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="optional legs that would start after this many seconds are skipped")
     ap.add_argument("--train-models", type=int, default=16,
                     help="seeded 80x80x50 models of the same family that give training pairs")
     ap.add_argument("--train-iters", type=int, default=1500)
     ap.add_argument("--kernels-only", action="store_true",
                     help="for hardware-counter runs: set up the first Newton system of the "
-                         "workload, then run 5 RAS applies, 5 V-cycles, 5 SpMVs and 5 copies "
+                         "workload, then run 5 RAS applies, 5 AMG cycles, 5 SpMVs and 5 copies "
                          "of 512 MiB (the traffic calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): this build has no "
               "multi-GPU decomposition", file=sys.stderr)
         sys.exit(2)
+    T0 = time.perf_counter()
 
     import torch
     import workloads
@@ -541,6 +597,7 @@ def main():
         return
     model = r2p.Model(w)
     x = model.initial_state()
+    x_init = x.clone()
     form = r2p.CPR_FPF if args.form == "fpf" else r2p.CPR_TWO_STAGE
     o64 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form))
     o32 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, precision=r2p.FP32))
@@ -567,6 +624,7 @@ def main():
                           "spmv_bytes": spmv_bytes(model), "copy_bytes": 2 * src.numel() * 8}))
         return
 
+    # ---- the timed region: plain FP64 steps of the controller
     dt, _ = run_steps(model, x, DT_INIT, args.warmup, o64, dt_max, "warmup")
     x0 = x.clone()
     torch.cuda.synchronize()
@@ -576,84 +634,7 @@ def main():
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
     s64 = summarise(recs)
     accepted = [r["dt"] for r in recs if r["status"] == 0]
-
-    fp32 = None
-    if not args.no_fp32:
-        x32 = x0.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, recs32 = run_steps(model, x32, dt, args.steps, o32, dt_max, "fp32", dts=accepted)
-        torch.cuda.synchronize()
-        ms32 = (time.perf_counter() - t0) * 1e3 / args.steps
-        s32 = summarise(recs32)
-        p64, s_64 = x[0:2 * model.n:2], x[1:2 * model.n:2]
-        p32, s_32 = x32[0:2 * model.n:2], x32[1:2 * model.n:2]
-        fp32 = dict(ms_per_step=round(ms32, 3), solve_ms=round(s32["solve_ms"], 3),
-                    setup_ms=round(s32["setup_ms"], 3),
-                    linear_its_per_solve=round(s32["its_per_solve"], 2),
-                    newton_its=s32["solves"],
-                    rel_err_p=float(torch.linalg.norm(p32 - p64) / torch.linalg.norm(p64)),
-                    rel_err_sw=float(torch.linalg.norm(s_32 - s_64) /
-                                     max(float(torch.linalg.norm(s_64)), 1e-300)),
-                    learned_warm_start=None)
-
-    learned = None
-    if not args.no_learned and not args.no_fp32:
-        learned = learned_run(args, model, x0, x, accepted, form, log)
-
-    # per-kernel timing on the last state's first Newton system
-    J = r2p.Jacobian(model)
-    bd = J.assemble(x, x, dt_next)
-    P = r2p.Cpr().setup(J, o64.cpr)
-    v = torch.randn(model.N, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(v)
-    fp = torch.randn(model.n, dtype=torch.float64, device="cuda")
-    xp = torch.empty_like(fp)
-    t_spmv = time_on_stream(lambda: J.spmv(v, y), 50)
-    t_ras = time_on_stream(lambda: P.ras_apply(v, y), 20)
-    t_amg = time_on_stream(lambda: P.amg_vcycle(fp, xp), 20)
-    t_cpr = time_on_stream(lambda: P.apply(v, y), 20)
-    rb, m_tot, nblk = ras_bytes(P, model, 8)
-    sb = spmv_bytes(model)
-    vb = vcycle_bytes(P, model, 8)
-    ras_gbs = rb / (t_ras * 1e-3) / 1e9
-    spmv_gbs = sb / (t_spmv * 1e-3) / 1e9
-    vcycle_gbs = vb / (t_amg * 1e-3) / 1e9
-    log(f"kernels: spmv {t_spmv * 1e3:.1f} us ({spmv_gbs:.0f} GB/s), ras {t_ras * 1e3:.1f} us "
-        f"({ras_gbs:.0f} GB/s), vcycle {t_amg * 1e3:.1f} us ({vcycle_gbs:.0f} GB/s), "
-        f"cpr {t_cpr * 1e3:.1f} us")
-    # the same Newton system solved by BiCGSTAB (two CPR applications per iteration)
-    krylov = {}
-    for name, method in (("fgmres", r2p.KRYLOV_FGMRES), ("bicgstab", r2p.KRYLOV_BICGSTAB)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, info = r2p.solve(J, P, bd, r2p.solve_opts(method=method))
-        torch.cuda.synchronize()
-        krylov[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 3),
-                        "iterations": info.iterations, "relres": info.relres,
-                        "status": info.status}
-    log(f"krylov on the last system: {krylov}")
-    variants = None if args.no_variants else variants_run(model, x, dt_next, form)
-    # inexact Newton with Eisenstat-Walker forcing on the timed steps' lengths
-    ew = None
-    if not args.no_variants:
-        oew = r2p.newton_opts(cpr=r2p.cpr_opts(form=form), forcing=r2p.FORCING_EW)
-        xe = x0.clone()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, recs_ew = run_steps(model, xe, dt, args.steps, oew, dt_max, "fp64+EW", dts=accepted)
-        torch.cuda.synchronize()
-        ms_ew = (time.perf_counter() - t0) * 1e3 / args.steps
-        sew = summarise(recs_ew)
-        p64, s_64 = x[0:2 * model.n:2], x[1:2 * model.n:2]
-        pe, se = xe[0:2 * model.n:2], xe[1:2 * model.n:2]
-        ew = dict(ms_per_step=round(ms_ew, 3), newton_its=sew["solves"],
-                  linear_its=sew["linear_its"], linear_its_per_solve=round(sew["its_per_solve"], 2),
-                  plain_newton_its=s64["solves"], plain_linear_its=s64["linear_its"],
-                  rel_err_p=float(torch.linalg.norm(pe - p64) / torch.linalg.norm(p64)),
-                  rel_err_sw=float(torch.linalg.norm(se - s_64) /
-                                   max(float(torch.linalg.norm(s_64)), 1e-300)))
-
+    n = model.n
     out = {
         "metric": METRIC, "value": round(s64["solve_ms"], 3), "unit": "ms", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
@@ -662,37 +643,162 @@ def main():
         "config": {"workload": f"{w['name']}: {w['grid']['n']} cells, {len(w['wells'])} wells, "
                                f"adaptive dt from {DT_INIT} d (max {dt_max} d); CPR {args.form}, "
                                "QI + local potential order, RAS 4x4 overlap 1 BILU(0), "
-                               "aggregation AMG V(1,1), FGMRES(30) rtol 1e-8",
+                               "aggregation AMG with K-cycle on the two finest levels, "
+                               "FGMRES(30) rtol 1e-8",
                    "cells": w["grid"]["n"], "form": args.form},
         "dt_days": accepted,
         "newton_its_per_step": round(s64["solves"] / args.steps, 2),
         "linear_its_per_solve": round(s64["its_per_solve"], 2),
         "setup_ms_per_solve": round(s64["setup_ms"], 3),
         "ms_per_fgmres_iteration": round(s64["solve_ms"] / max(s64["its_per_solve"], 1e-9), 4),
-        "kernels_us": {"spmv": round(t_spmv * 1e3, 2), "ras_apply": round(t_ras * 1e3, 2),
-                       "amg_vcycle": round(t_amg * 1e3, 2), "cpr_apply": round(t_cpr * 1e3, 2)},
-        "spmv_gbs": round(spmv_gbs, 1),
-        "spmv_hbm_frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
-        "vcycle_bytes": vb,
-        "vcycle_gbs": round(vcycle_gbs, 1),
-        "vcycle_hbm_frac": round(vcycle_gbs / HBM_PEAK_GBS, 4),
-        "krylov_last_system": krylov,
-        "variants_last_system": variants,
-        "inexact_newton_ew": ew,
-        "roofline": {"bound": "hbm", "kernel": "ras_apply (k_ras_gather+k_ras_sweep+k_ras_scatter)",
-                     "achieved": round(ras_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ras_gbs / HBM_PEAK_GBS, 4), "traffic": ras_traffic(),
-                     "bytes_per_launch": rb, "local_rows": m_tot, "offdiag_blocks": nblk},
-        "fp32": fp32,
-        "fp32_learned": learned,
+        "stage_ms_per_step": stage_summary(recs),
+        "step_records": [{k: (round(v, 2) if isinstance(v, float) else v) for k, v in r.items()}
+                         for r in recs],
+        "errors": {},
     }
-    if not args.no_cpu_baseline:
+    log(f"fp64: {ms_step:.0f} ms per step, {s64['solve_ms']:.1f} ms per solve, "
+        f"{s64['its_per_solve']:.1f} iterations per solve")
+
+    def leg(name, fn, required=False):
+        """Run an optional leg; its failure is recorded, never fatal."""
+        el = time.perf_counter() - T0
+        if not required and el > args.budget_s:
+            out["errors"][name] = f"skipped: {el:.0f} s elapsed (budget {args.budget_s:.0f} s)"
+            log(out["errors"][name])
+            return None
         try:
-            out["cpu_baseline"] = cpu_baseline(w, s64["its_per_solve"], DT_INIT,
-                                               args.cpu_sample_its)
-        except Exception as e:  # the baseline is reported, never required
-            log(f"cpu baseline failed: {e}")
-            out["cpu_baseline"] = None
+            return fn()
+        except Exception as e:   # recorded in the JSON line, the measurement is kept
+            out["errors"][name] = f"{type(e).__name__}: {e}"
+            log(f"{name} failed: {e}")
+            return None
+
+    # ---- FP32 preconditioner replay of the same steps (timed)
+    def fp32_leg():
+        x32 = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, recs32 = run_steps(model, x32, dt, args.steps, o32, dt_max, "fp32", dts=accepted)
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t0) * 1e3 / args.steps
+        s32 = summarise(recs32)
+        p64, s_64 = x[0:2 * n:2], x[1:2 * n:2]
+        p32, s_32 = x32[0:2 * n:2], x32[1:2 * n:2]
+        return dict(ms_per_step=round(ms32, 3), solve_ms=round(s32["solve_ms"], 3),
+                    setup_ms=round(s32["setup_ms"], 3),
+                    linear_its_per_solve=round(s32["its_per_solve"], 2),
+                    newton_its=s32["solves"], stage_ms_per_step=stage_summary(recs32),
+                    rel_err_p=float(torch.linalg.norm(p32 - p64) / torch.linalg.norm(p64)),
+                    rel_err_sw=float(torch.linalg.norm(s_32 - s_64) /
+                                     max(float(torch.linalg.norm(s_64)), 1e-300)))
+    out["fp32"] = None if args.no_fp32 else leg("fp32", fp32_leg)
+
+    # ---- per-kernel timing and the roofline on the last state's first system
+    def kernel_leg():
+        J = r2p.Jacobian(model)
+        J.assemble(x, x, dt_next)
+        P = r2p.Cpr().setup(J, o64.cpr)
+        v = torch.randn(model.N, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(v)
+        fp = torch.randn(model.n, dtype=torch.float64, device="cuda")
+        xp = torch.empty_like(fp)
+        t_spmv = time_on_stream(lambda: J.spmv(v, y), 50)
+        t_ras = time_on_stream(lambda: P.ras_apply(v, y), 20)
+        t_amg = time_on_stream(lambda: P.amg_vcycle(fp, xp), 20)
+        t_cpr = time_on_stream(lambda: P.apply(v, y), 20)
+        rb, m_tot, nblk = ras_bytes(P, model, 8)
+        sb = spmv_bytes(model)
+        J.assemble(x, x, dt_next)
+        Pv = r2p.Cpr().setup(J, r2p.cpr_opts(form=form, kcycle=0))
+        t_v = time_on_stream(lambda: Pv.amg_vcycle(fp, xp), 20)
+        vb = vcycle_bytes(Pv, model, 8)
+        ras_gbs = rb / (t_ras * 1e-3) / 1e9
+        spmv_gbs = sb / (t_spmv * 1e-3) / 1e9
+        vcycle_gbs = vb / (t_v * 1e-3) / 1e9
+        log(f"kernels: spmv {t_spmv * 1e3:.1f} us ({spmv_gbs:.0f} GB/s), ras {t_ras * 1e3:.1f} us "
+            f"({ras_gbs:.0f} GB/s), K-cycle {t_amg * 1e3:.1f} us, V-cycle {t_v * 1e3:.1f} us "
+            f"({vcycle_gbs:.0f} GB/s), cpr {t_cpr * 1e3:.1f} us")
+        out.update({
+            "kernels_us": {"spmv": round(t_spmv * 1e3, 2), "ras_apply": round(t_ras * 1e3, 2),
+                           "amg_kcycle": round(t_amg * 1e3, 2), "amg_vcycle": round(t_v * 1e3, 2),
+                           "cpr_apply": round(t_cpr * 1e3, 2)},
+            "amg_levels": [g["n"] for g in P.amg_levels()],
+            "spmv_gbs": round(spmv_gbs, 1), "spmv_hbm_frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
+            "vcycle_bytes": vb, "vcycle_gbs": round(vcycle_gbs, 1),
+            "vcycle_hbm_frac": round(vcycle_gbs / HBM_PEAK_GBS, 4),
+            "roofline": {"bound": "hbm",
+                         "kernel": "ras_apply (k_ras_gather+k_ras_sweep+k_ras_scatter)",
+                         "achieved": round(ras_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ras_gbs / HBM_PEAK_GBS, 4), "traffic": ras_traffic(),
+                         "bytes_per_launch": rb, "local_rows": m_tot, "offdiag_blocks": nblk}})
+        return True
+    leg("kernels", kernel_leg, required=True)
+
+    # ---- fixed-snapshot solves at the 10-day step length
+    out["snapshot_solves"] = leg("snapshots", lambda: snapshot_solves(
+        model, [("cold start", x_init), (f"after {args.warmup} warm-up steps", x0),
+                (f"after {args.warmup + args.steps} steps", x)], dt_max, form, log))
+
+    # ---- the oracle on the host
+    def cpu_leg():
+        c = cpu_baseline(w, s64["its_per_solve"], DT_INIT, args.cpu_sample_its)
+        cpu_model, ncpu = host_cpu()
+        c["sample"] += f"; host: {cpu_model}, {ncpu} logical CPUs, the oracle used 1"
+        c["cpu_model"] = cpu_model
+        c["host_cpus"] = ncpu
+        return c
+    out["cpu_baseline"] = None if args.no_cpu_baseline else leg("cpu_baseline", cpu_leg)
+
+    # ---- inexact Newton with Eisenstat-Walker forcing on the timed steps' lengths
+    def ew_leg():
+        oew = r2p.newton_opts(cpr=r2p.cpr_opts(form=form), forcing=r2p.FORCING_EW)
+        xe = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, recs_ew = run_steps(model, xe, dt, args.steps, oew, dt_max, "fp64+EW", dts=accepted)
+        torch.cuda.synchronize()
+        ms_ew = (time.perf_counter() - t0) * 1e3 / args.steps
+        sew = summarise(recs_ew)
+        p64, s_64 = x[0:2 * n:2], x[1:2 * n:2]
+        pe, se = xe[0:2 * n:2], xe[1:2 * n:2]
+        return dict(ms_per_step=round(ms_ew, 3), newton_its=sew["solves"],
+                    linear_its=sew["linear_its"],
+                    linear_its_per_solve=round(sew["its_per_solve"], 2),
+                    plain_newton_its=s64["solves"], plain_linear_its=s64["linear_its"],
+                    step_failures=sum(1 for r in recs_ew if r["status"] != 0),
+                    rel_err_p=float(torch.linalg.norm(pe - p64) / torch.linalg.norm(p64)),
+                    rel_err_sw=float(torch.linalg.norm(se - s_64) /
+                                     max(float(torch.linalg.norm(s_64)), 1e-300)))
+    out["inexact_newton_ew"] = None if args.no_variants else leg("ew", ew_leg)
+
+    # ---- Krylov methods and the method variants on the last Newton system
+    def krylov_leg():
+        res = {}
+        for name, method, kc in (("fgmres", r2p.KRYLOV_FGMRES, 2),
+                                 ("fgmres_vcycle", r2p.KRYLOV_FGMRES, 0),
+                                 ("bicgstab_vcycle", r2p.KRYLOV_BICGSTAB, 0)):
+            J = r2p.Jacobian(model)
+            bd = J.assemble(x, x, dt_next)
+            P = r2p.Cpr().setup(J, r2p.cpr_opts(form=form, kcycle=kc))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = r2p.solve(J, P, bd, r2p.solve_opts(method=method))
+            torch.cuda.synchronize()
+            res[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 3),
+                         "iterations": info.iterations, "relres": info.relres,
+                         "status": info.status}
+        log(f"krylov on the last system: {res}")
+        return res
+    out["krylov_last_system"] = None if args.no_variants else leg("krylov", krylov_leg)
+    out["variants_last_system"] = None if args.no_variants else leg(
+        "variants", lambda: variants_run(model, x, dt_next, form))
+
+    # ---- FP32 preconditioner + learned warm start
+    out["fp32_learned"] = None
+    if not args.no_learned and not args.no_fp32:
+        out["fp32_learned"] = leg("learned", lambda: learned_run(args, model, x0, x, accepted,
+                                                                 form, log))
+    out["wall_s"] = round(time.perf_counter() - T0, 1)
     print(json.dumps(out), flush=True)
 
 

@@ -100,6 +100,11 @@ typedef struct {
     int match_rounds;  /* AMG: handshake rounds per pairwise matching (4) */
     int agg_passes;    /* AMG: aggregation passes per level (1 or 2; 2 gives aggregates of ~4) */
     int precision;     /* R2P_FP64, or R2P_FP32: AMG and ILU stored and applied in FP32 */
+    int kcycle;        /* AMG: the coarse correction of the kcycle finest levels is two
+                          generalised-conjugate-residual steps, each preconditioned by a
+                          cycle one level down (K-cycle); 0 gives the V-cycle.  A K-cycle
+                          makes the preconditioner vary with its input: use it with the
+                          flexible GMRES, not with BiCGSTAB (2) */
 } r2p_cpr_opts;
 
 enum { R2P_KRYLOV_FGMRES = 0, R2P_KRYLOV_BICGSTAB = 1 };
@@ -135,6 +140,22 @@ typedef struct {
 enum { R2P_GUESS_SCALED_INF = 0, R2P_GUESS_L2 = 1, R2P_GUESS_TRY = 2 };
 
 #define R2P_HIST 32
+/* Host wall times (ms) summed over the step's Newton iterations, stage by
+ * stage as the paper's timing table splits the linear solve (Table 5):
+ *   ms_assemble   residual, Jacobian and the scaled-norm test;
+ *   ms_setup      the whole CPR set-up (r2p_setup_cpr), made of
+ *     ms_decouple   decoupling D^-1 A (QI or ABF, Eq 29),
+ *     ms_order      local potential reordering (dependency levels, local
+ *                   order, Eq 30-33),
+ *     ms_ras_setup  block ILU(0) of every subdomain,
+ *     ms_amg_setup  the AMG hierarchy; it runs on its own host thread and
+ *                   stream beside ms_order + ms_ras_setup, so ms_setup is
+ *                   about ms_decouple + max(ms_order + ms_ras_setup,
+ *                   ms_amg_setup);
+ *   ms_solve      the Krylov solves (r2p_solve);
+ *   ms_update     the Newton update (and the linear residual norm of EW);
+ *   ms_total      the whole call: ms_assemble + ms_setup + ms_solve +
+ *                 ms_update plus the warm-start test and copies. */
 typedef struct {
     int status;              /* 0 converged, 1 not converged (x unchanged) */
     int newton_its;
@@ -142,6 +163,10 @@ typedef struct {
     int used_guess;          /* 1 if x_guess was taken as the first iterate */
     double res_hist[R2P_HIST];   /* scaled residual norm per Newton iteration */
     double ms_assemble, ms_setup, ms_solve, ms_total;
+    double ms_decouple, ms_order, ms_ras_setup, ms_amg_setup, ms_update;
+    int setup_status;        /* status of the last CPR set-up: 0, or the failure of the
+                                method that ended the step (R2P_NOT_CONVERGED for a stalled
+                                AMG coarsening, R2P_ESINGULAR for a singular pivot) */
 } r2p_newton_info;
 
 /* ----------------------------------------------------------------- model */
@@ -198,7 +223,11 @@ int r2p_cpr_destroy(r2p_cpr *P);
  * stage) and the aggregation AMG hierarchy of the pressure block A_pp
  * (restriction Pi_r of Eq 34).  Synchronises `stream` (level counts and
  * coarse sizes are read back).  J must have been assembled since its last
- * setup.  Errors: R2P_ESTATE, R2P_EINVAL, R2P_ESINGULAR, R2P_ENOMEM. */
+ * setup.  Returns 0; R2P_NOT_CONVERGED (a soft failure of the method) when
+ * the AMG coarsening stalls with a coarsest level above the dense limit of
+ * 4096 rows; or an error: R2P_ESTATE, R2P_EINVAL, R2P_ESINGULAR (singular
+ * pivot block), R2P_ENOMEM.  The handle is not usable for solves after a
+ * non-zero return until it is set up again. */
 int r2p_setup_cpr(r2p_jacobian *J, const r2p_cpr_opts *opts, r2p_cpr *P, void *stream);
 
 /* z[N] <- M^-1 f[N] for the decoupled system (two-stage form or Algorithm 2). */

@@ -103,37 +103,67 @@ __device__ __forceinline__ void take_stronger(double &s, int &j, double s2, int 
     if (j2 >= 0 && (j < 0 || s2 > s || (s2 == s && j2 < j))) { s = s2; j = j2; }
 }
 
-__global__ void k_strength_thr(int n, const int *rp, const int *col, const double *val,
-                               double theta, double *thr, int *match) {
+// a_ji by binary search of row j (columns ascend), 0 when j stores no i.
+__device__ __forceinline__ double entry_of(const int *rp, const int *col, const double *val, int j,
+                                           int i) {
+    int lo = rp[j], hi = rp[j + 1];
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        int c = col[mid];
+        if (c == i) return val[mid];
+        if (c < i) lo = mid + 1;
+        else hi = mid;
+    }
+    return 0.0;
+}
+
+// Coupling weights w[z] = -(a_ij + a_ji)/2 of every stored off-diagonal
+// entry z = (i, j) (0 on the diagonal), the same number from either row,
+// and M_i = max(0, max_j w_ij).
+__global__ void k_weights(int n, const int *rp, const int *col, const double *val, double *w,
+                          double *M, int *match) {
     int i, g;
     row_group(n, i, g);
     if (i >= n) return;                        // whole groups leave together
     double mx = 0.0;
-    for (int z = rp[i] + g; z < rp[i + 1]; z += GS)
-        if (col[z] != i && -val[z] > mx) mx = -val[z];
+    for (int z = rp[i] + g; z < rp[i + 1]; z += GS) {
+        int j = col[z];
+        double wz = 0.0;
+        if (j != i) wz = -(val[z] + entry_of(rp, col, val, j, i)) / 2.0;
+        w[z] = wz;
+        if (wz > mx) mx = wz;
+    }
     for (int d = 1; d < GS; d <<= 1) mx = fmax(mx, __shfl_xor(mx, d, 64));
     if (g == 0) {
-        thr[i] = theta * mx;
+        M[i] = mx;
         match[i] = -1;
     }
+}
+
+// The symmetric strength relation: w_ij > 0 and w_ij reaches theta of the
+// largest weight of row i or of row j.
+__device__ __forceinline__ bool strong_pair(double wij, double Mi, double Mj, double theta) {
+    return wij > 0.0 && (wij >= theta * Mi || wij >= theta * Mj);
 }
 
 // Strongest strong neighbour j of an unmatched row i with match[j] < 0
 // (propose) or >= 0 (join), ties to the smaller column; -1 if none.
 template <bool JOIN>
-__device__ __forceinline__ void strongest(int n, const int *rp, const int *col, const double *val,
-                                          const double *thr, const int *match, int *out) {
+__device__ __forceinline__ void strongest(int n, const int *rp, const int *col, const double *w,
+                                          const double *M, double theta, const int *match,
+                                          int *out) {
     int i, g;
     row_group(n, i, g);
     if (i >= n) return;
     double best = 0.0;
     int best_j = -1;
     if (match[i] < 0) {
+        double Mi = M[i];
         for (int z = rp[i] + g; z < rp[i + 1]; z += GS) {
             int j = col[z];
-            double s = -val[z];
+            double s = w[z];
             bool free_j = match[j] < 0;
-            if (j == i || free_j == JOIN || !(s > 0.0) || s < thr[i]) continue;
+            if (j == i || free_j == JOIN || !strong_pair(s, Mi, M[j], theta)) continue;
             if (s > best) { best = s; best_j = j; }
         }
     }
@@ -145,9 +175,9 @@ __device__ __forceinline__ void strongest(int n, const int *rp, const int *col, 
     if (g == 0) out[i] = best_j;
 }
 
-__global__ void k_propose(int n, const int *rp, const int *col, const double *val,
-                          const double *thr, const int *match, int *prop) {
-    strongest<false>(n, rp, col, val, thr, match, prop);
+__global__ void k_propose(int n, const int *rp, const int *col, const double *w, const double *M,
+                          double theta, const int *match, int *prop) {
+    strongest<false>(n, rp, col, w, M, theta, match, prop);
 }
 
 __global__ void k_accept(int n, const int *prop, int *match) {
@@ -158,9 +188,9 @@ __global__ void k_accept(int n, const int *prop, int *match) {
 }
 
 // Unmatched rows: strongest strong neighbour that is in a pair (or -1).
-__global__ void k_join(int n, const int *rp, const int *col, const double *val, const double *thr,
-                       const int *match, int *jt) {
-    strongest<true>(n, rp, col, val, thr, match, jt);
+__global__ void k_join(int n, const int *rp, const int *col, const double *w, const double *M,
+                       double theta, const int *match, int *jt) {
+    strongest<true>(n, rp, col, w, M, theta, match, jt);
 }
 
 __global__ void k_leader_flag(int n, const int *match, const int *jt, int *flag) {
@@ -458,26 +488,28 @@ static int galerkin(r2p_cpr *P, int n, int nnz, const int *rp, const int *col, c
 }
 
 // One aggregation pass: agg (row -> aggregate) and the aggregate count.
-static int aggregate_pass(r2p_cpr *P, int n, const int *rp, const int *col, const double *val,
-                          DBuf<int> &agg, int *nc, hipStream_t s) {
+static int aggregate_pass(r2p_cpr *P, int n, int nnz, const int *rp, const int *col,
+                          const double *val, DBuf<int> &agg, int *nc, hipStream_t s) {
     SetupWork &W = P->aws;
-    DBuf<double> &thr = W.d[0];
+    DBuf<double> &M = W.d[0], &wgt = W.d[1];
     DBuf<int> &match = W.i[0], &prop = W.i[1], &flag = W.i[2], &jt = W.i[3];
-    R2P_TRY(thr.ensure(n));
+    R2P_TRY(M.ensure(n));
+    R2P_TRY(wgt.ensure(nnz));
     R2P_TRY(match.ensure(n));
     R2P_TRY(prop.ensure(n));
     R2P_TRY(jt.ensure(n));
     R2P_TRY(flag.ensure(n + 1));
     int nb = r2p_blocks(n, BS), ng = r2p_blocks(n, BS / GS);
-    k_strength_thr<<<ng, BS, 0, s>>>(n, rp, col, val, P->o.theta, thr.p, match.p);
+    double th = P->o.theta;
+    k_weights<<<ng, BS, 0, s>>>(n, rp, col, val, wgt.p, M.p, match.p);
     R2P_LAUNCH();
     for (int r = 0; r < P->o.match_rounds; r++) {
-        k_propose<<<ng, BS, 0, s>>>(n, rp, col, val, thr.p, match.p, prop.p);
+        k_propose<<<ng, BS, 0, s>>>(n, rp, col, wgt.p, M.p, th, match.p, prop.p);
         R2P_LAUNCH();
         k_accept<<<nb, BS, 0, s>>>(n, prop.p, match.p);
         R2P_LAUNCH();
     }
-    k_join<<<ng, BS, 0, s>>>(n, rp, col, val, thr.p, match.p, jt.p);
+    k_join<<<ng, BS, 0, s>>>(n, rp, col, wgt.p, M.p, th, match.p, jt.p);
     R2P_LAUNCH();
     k_leader_flag<<<nb, BS, 0, s>>>(n, match.p, jt.p, flag.p);
     R2P_LAUNCH();
@@ -556,7 +588,7 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
         int cn = A.n, nc = A.n, nnzc = 0, cnnz = A.nnz;
         for (int p = 0; p < passes; p++) {
             DBuf<int> &a = P->aws.agg;
-            R2P_TRY(aggregate_pass(P, cn, rp, col, val, a, &nc, s));
+            R2P_TRY(aggregate_pass(P, cn, cnnz, rp, col, val, a, &nc, s));
             bool last = p == passes - 1;
             DBuf<int> &orp = last ? C.rp : crp[p & 1];
             DBuf<int> &ocol = last ? C.col : ccol[p & 1];
@@ -597,11 +629,22 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
         R2P_TRY(A.b.ensure(A.n));
         R2P_TRY(A.x.ensure(A.n));
         R2P_TRY(A.xo.ensure(A.n));
+        // K-cycle work vectors on the levels whose systems the K-cycle solves
+        if (k >= 1 && k <= P->o.kcycle && k < P->nlev - 1) {
+            if (f32) R2P_TRY(A.kvf.ensure(4L * A.n));
+            else R2P_TRY(A.kv.ensure(4L * A.n));
+        }
     }
+    R2P_TRY(P->kscal.ensure(4 * 24));
+    R2P_TRY(P->kpart.ensure(2 * 256));
     // coarsest level: dense LU and inverse (FP64)
     AmgLevel &C = P->lv[P->nlev - 1];
     int nc = C.n;
-    if (nc > 4096) { r2p_set_error("coarsest AMG level too large (%d rows)", nc); return R2P_EINVAL; }
+    if (nc > 4096) {
+        // coarsening stalled: a soft failure of the method (no dense solve of that size)
+        r2p_set_error("AMG coarsening stalled: coarsest level of %d rows", nc);
+        return R2P_NOT_CONVERGED;
+    }
     P->ncoarse = nc;
     R2P_TRY(P->lu.ensure((size_t)nc * nc));
     R2P_TRY(P->cinv.ensure((size_t)nc * nc));
@@ -644,7 +687,9 @@ struct CsrArgs {
     T *xo;                       // down: residual b - A x; up: x + (b - A x) / d
 };
 
-template <class T, bool UP>
+// MODE: CSR_DOWN xo = b - A x; CSR_UP xo = x + (b - A x) / d; CSR_PRODUCT xo = A x.
+enum { CSR_DOWN = 0, CSR_UP = 1, CSR_PRODUCT = 2 };
+template <class T, int MODE>
 __global__ __launch_bounds__(256) void k_csr_level(CsrArgs<T> A) {
     int i, lane0;
     T acc = (T)0;
@@ -681,7 +726,9 @@ __global__ __launch_bounds__(256) void k_csr_level(CsrArgs<T> A) {
         }
         for (int d = 1; d < 64; d <<= 1) acc += __shfl_xor(acc, d, 64);
     }
-    if (lane0 == 0) A.xo[i] = UP ? A.x[i] + (A.b[i] - acc) / A.l1[i] : A.b[i] - acc;
+    if (lane0 == 0)
+        A.xo[i] = MODE == CSR_UP ? A.x[i] + (A.b[i] - acc) / A.l1[i]
+                                 : (MODE == CSR_DOWN ? A.b[i] - acc : acc);
 }
 
 // Restriction P^T r: a group of GR lanes per coarse row (lanes stride over
@@ -819,90 +866,237 @@ __global__ __launch_bounds__(64 * CS_WAVES) void k_coarse_solve(int n, const dou
     else x[i] = (T)t;
 }
 
+// ------------------------------------------------------------- K-cycle
+// Two generalised-conjugate-residual steps on a coarse level c (the
+// corrections of the `kcycle` finest levels): p1 = C(b), q1 = A p1,
+// a1 = (q1.b)/(q1.q1), r = b - a1 q1; p2 = C(r), q2 = A p2,
+// beta = (q1.q2)/(q1.q1), p2 -= beta p1, q2 -= beta q1, a2 = (q2.r)/(q2.q2);
+// the correction a1 p1 + a2 p2 is added by the prolongation.  The scalars
+// stay on the device: each group of dot products is summed per workgroup,
+// then in workgroup order by one workgroup that also forms the scalar, so
+// nothing is read back and the sums do not depend on scheduling.
+constexpr int KD_BLOCKS = 256;
 template <class T>
-static int vcycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStream_t s) {
-    int nl = P->nlev;
-    auto vals = [&](AmgLevel &A) -> const T * {
+__global__ __launch_bounds__(BS) void k_kdots(int n, const T *a0, const T *b0, const T *a1,
+                                              const T *b1, double *part) {
+    __shared__ double red[2][BS / 64];
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) {
+        s0 += (double)a0[i] * (double)b0[i];
+        if (a1) s1 += (double)a1[i] * (double)b1[i];
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        s0 += __shfl_xor(s0, d, 64);
+        s1 += __shfl_xor(s1, d, 64);
+    }
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) { red[0][wv] = s0; red[1][wv] = s1; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int q = 0; q < BS / 64; q++) { t0 += red[0][q]; t1 += red[1][q]; }
+        part[blockIdx.x] = t0;
+        part[gridDim.x + blockIdx.x] = t1;
+    }
+}
+
+// ks = {q1.q1, a1, beta, a2}.  step 0: from (q1.q1, q1.b); 1: from q1.q2;
+// 2: from (q2.q2, q2.r).  A zero denominator gives a zero step.
+__global__ __launch_bounds__(BS) void k_kfin(int nb, const double *part, int step, double *ks) {
+    __shared__ double red[2][BS / 64];
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BS) { s0 += part[b]; s1 += part[nb + b]; }
+    for (int d = 32; d > 0; d >>= 1) {
+        s0 += __shfl_xor(s0, d, 64);
+        s1 += __shfl_xor(s1, d, 64);
+    }
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) { red[0][wv] = s0; red[1][wv] = s1; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double t0 = 0.0, t1 = 0.0;
+    for (int q = 0; q < BS / 64; q++) { t0 += red[0][q]; t1 += red[1][q]; }
+    if (step == 0) {
+        ks[0] = t0;
+        ks[1] = t0 > 0.0 ? t1 / t0 : 0.0;
+    } else if (step == 1) {
+        ks[2] = ks[0] > 0.0 ? t0 / ks[0] : 0.0;
+    } else {
+        ks[3] = t0 > 0.0 ? t1 / t0 : 0.0;
+    }
+}
+
+// r = b - a1 q1 (in place of b) and the next cycle's pre-smoothed iterate r / d.
+template <class T>
+__global__ void k_kres(int n, T *b, const T *q1, const double *ks, const T *l1, T *x) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T r = (T)((double)b[i] - ks[1] * (double)q1[i]);
+    b[i] = r;
+    x[i] = r / l1[i];
+}
+
+// p2 -= beta p1, q2 -= beta q1.
+template <class T>
+__global__ void k_korth(int n, const T *p1, T *p2, const T *q1, T *q2, const double *ks) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double beta = ks[2];
+    p2[i] = (T)((double)p2[i] - beta * (double)p1[i]);
+    q2[i] = (T)((double)q2[i] - beta * (double)q1[i]);
+}
+
+// Prolongation of the K-cycle correction: x_j += a1 p1[agg_j] + a2 p2[agg_j].
+template <class T>
+__global__ void k_prolong_k(int n, const int *agg, const T *p1, const T *p2, const double *ks,
+                            T *x) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int I = agg[j];
+    T c = (T)(ks[1] * (double)p1[I] + ks[3] * (double)p2[I]);
+    x[j] = x[j] + c;
+}
+
+// --------------------------------------------------------------- cycle
+template <class T>
+struct Cycle {
+    r2p_cpr *P;
+    hipStream_t s;
+    int nl;
+    static const T *vals(AmgLevel &A) {
         if constexpr (sizeof(T) == 4) return A.f32.val.p; else return (const T *)A.val.p;
-    };
-    auto l1s = [&](AmgLevel &A) -> const T * {
+    }
+    static const T *l1s(AmgLevel &A) {
         if constexpr (sizeof(T) == 4) return A.f32.l1.p; else return (const T *)A.l1.p;
-    };
-    auto vb = [&](AmgLevel &A) -> T * {
+    }
+    static T *vb(AmgLevel &A) {
         if constexpr (sizeof(T) == 4) return A.bf.p; else return (T *)A.b.p;
-    };
-    auto vx = [&](AmgLevel &A) -> T * {
+    }
+    static T *vx(AmgLevel &A) {
         if constexpr (sizeof(T) == 4) return A.xf.p; else return (T *)A.x.p;
-    };
-    auto vxo = [&](AmgLevel &A) -> T * {
+    }
+    static T *vxo(AmgLevel &A) {
         if constexpr (sizeof(T) == 4) return A.xof.p; else return (T *)A.xo.p;
-    };
-    auto csr_args = [&](AmgLevel &A) {
+    }
+    static T *kv(AmgLevel &A) {
+        if constexpr (sizeof(T) == 4) return A.kvf.p; else return (T *)A.kv.p;
+    }
+    CsrArgs<T> csr(AmgLevel &A, const T *x, T *xo) {
         CsrArgs<T> a;
         a.n = A.n; a.nbs = r2p_blocks(A.n, BS / G);
         a.heavy = A.heavy.p; a.nheavy = A.nheavy;
         a.rp = A.rp.p; a.col = A.col.p; a.val = vals(A); a.l1 = l1s(A);
         a.b = vb(A);
-        a.x = nullptr; a.xo = nullptr;
+        a.x = x; a.xo = xo;
         return a;
-    };
-    if (nl == 1) {
-        AmgLevel &C = P->lv[0];
-        k_coarse_solve<T><<<r2p_blocks(C.n, 64), 64 * CS_WAVES, 0, s>>>(
-            C.n, P->cinv.p, vb(C), f, fstride, vx(C), xp);
+    }
+    template <int MODE>
+    int csr_launch(AmgLevel &A, const T *x, T *xo) {
+        CsrArgs<T> D = csr(A, x, xo);
+        k_csr_level<T, MODE><<<D.nbs + r2p_blocks(A.nheavy, BS / 64), BS, 0, s>>>(D);
         R2P_LAUNCH();
         return 0;
     }
-    const Phys &ph = P->J->m->ph;
-    Level0<T> Z;
-    Z.n = P->lv[0].n; Z.nx = ph.nx; Z.nxy = ph.nx * ph.ny;
-    if constexpr (sizeof(T) == 4) Z.v7 = P->lv[0].v7f.p; else Z.v7 = (const T *)P->lv[0].v7.p;
-    Z.l1 = l1s(P->lv[0]);
-    Z.f = f;
-    Z.fstride = fstride;
-    for (int l = 0; l < nl - 1; l++) {
-        AmgLevel &A = P->lv[l];
-        AmgLevel &C = P->lv[l + 1];
-        // the level's output buffer holds its residual until the up sweep
-        if (l == 0) {
-            k_down0<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(Z, vx(A), vxo(A));
-        } else {
-            CsrArgs<T> D = csr_args(A);
-            D.x = vx(A); D.xo = vxo(A);
-            k_csr_level<T, false><<<D.nbs + r2p_blocks(A.nheavy, BS / 64), BS, 0, s>>>(D);
-        }
-        R2P_LAUNCH();
+    // Restriction of level l's residual (in its xo) to level l+1's right-hand
+    // side, with l+1's pre-smoothed iterate when l+1 is smoothed.
+    int restrict_to(int l) {
+        AmgLevel &A = P->lv[l], &C = P->lv[l + 1];
         bool smooth = l + 1 < nl - 1;
         int nbs = r2p_blocks(C.n, BS / GR);
         k_restrict<T><<<nbs + r2p_blocks(A.nbig, BS / 64), BS, 0, s>>>(
             C.n, nbs, A.mptr.p, A.mem.p, A.big.p, A.nbig, vxo(A), vb(C),
             smooth ? l1s(C) : nullptr, smooth ? vx(C) : nullptr);
         R2P_LAUNCH();
+        return 0;
     }
-    AmgLevel &Cst = P->lv[nl - 1];
-    k_coarse_solve<T><<<r2p_blocks(Cst.n, 64), 64 * CS_WAVES, 0, s>>>(
-        Cst.n, P->cinv.p, vb(Cst), nullptr, 1, vxo(Cst), nullptr);
-    R2P_LAUNCH();
-    for (int l = nl - 2; l >= 1; l--) {
-        AmgLevel &A = P->lv[l];
-        AmgLevel &C = P->lv[l + 1];
-        k_prolong<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, A.agg.p, vxo(C), vx(A));
+    int dots(int n, const T *a0, const T *b0, const T *a1, const T *b1, int step, double *ks) {
+        int nb = std::max(1, std::min(KD_BLOCKS, r2p_blocks(n, BS)));
+        k_kdots<T><<<nb, BS, 0, s>>>(n, a0, b0, a1, b1, P->kpart.p);
         R2P_LAUNCH();
-        CsrArgs<T> U = csr_args(A);
-        U.x = vx(A); U.xo = vxo(A);
-        k_csr_level<T, true><<<U.nbs + r2p_blocks(A.nheavy, BS / 64), BS, 0, s>>>(U);
+        k_kfin<<<1, BS, 0, s>>>(nb, P->kpart.p, step, ks);
         R2P_LAUNCH();
+        return 0;
     }
-    k_prolong<T><<<r2p_blocks(Z.n, BS), BS, 0, s>>>(Z.n, P->lv[0].agg.p, vxo(P->lv[1]), vx(P->lv[0]));
-    R2P_LAUNCH();
-    k_up0<T><<<r2p_blocks(Z.n, BS), BS, 0, s>>>(Z, vx(P->lv[0]), xp);
-    R2P_LAUNCH();
-    return 0;
-}
+    // The coarse correction of level l, added to level l's iterate vx(l).
+    int correct(int l) {
+        AmgLevel &A = P->lv[l], &C = P->lv[l + 1];
+        int c = l + 1;
+        if (l < P->o.kcycle && c < nl - 1) {
+            int n = C.n;
+            T *p1 = kv(C), *p2 = p1 + n, *q1 = p2 + n, *q2 = q1 + n;
+            double *ks = P->kscal.p + 4 * c;
+            R2P_TRY(coarse(c, p1));
+            R2P_TRY(csr_launch<CSR_PRODUCT>(C, p1, q1));
+            R2P_TRY(dots(n, q1, q1, q1, vb(C), 0, ks));
+            k_kres<T><<<r2p_blocks(n, BS), BS, 0, s>>>(n, vb(C), q1, ks, l1s(C), vx(C));
+            R2P_LAUNCH();
+            R2P_TRY(coarse(c, p2));
+            R2P_TRY(csr_launch<CSR_PRODUCT>(C, p2, q2));
+            R2P_TRY(dots(n, q1, q2, nullptr, nullptr, 1, ks));
+            k_korth<T><<<r2p_blocks(n, BS), BS, 0, s>>>(n, p1, p2, q1, q2, ks);
+            R2P_LAUNCH();
+            R2P_TRY(dots(n, q2, q2, q2, vb(C), 2, ks));
+            k_prolong_k<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, A.agg.p, p1, p2, ks, vx(A));
+            R2P_LAUNCH();
+        } else {
+            R2P_TRY(coarse(c, vxo(C)));
+            k_prolong<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, A.agg.p, vxo(C), vx(A));
+            R2P_LAUNCH();
+        }
+        return 0;
+    }
+    // One cycle on a coarse (CSR) level c >= 1 whose right-hand side is in
+    // vb(c) and, unless c is the coarsest, pre-smoothed iterate in vx(c);
+    // the result goes to out.
+    int coarse(int c, T *out) {
+        AmgLevel &A = P->lv[c];
+        if (c == nl - 1) {
+            k_coarse_solve<T><<<r2p_blocks(A.n, 64), 64 * CS_WAVES, 0, s>>>(
+                A.n, P->cinv.p, vb(A), nullptr, 1, out, nullptr);
+            R2P_LAUNCH();
+            return 0;
+        }
+        // the level's xo holds its residual until the correction is added
+        R2P_TRY(csr_launch<CSR_DOWN>(A, vx(A), vxo(A)));
+        R2P_TRY(restrict_to(c));
+        R2P_TRY(correct(c));
+        return csr_launch<CSR_UP>(A, vx(A), out);
+    }
+    // The cycle from level 0 (7-slot stencil) with right-hand side f (stride
+    // fstride), result in xp.
+    int run(const double *f, int fstride, double *xp) {
+        if (nl == 1) {
+            AmgLevel &C = P->lv[0];
+            k_coarse_solve<T><<<r2p_blocks(C.n, 64), 64 * CS_WAVES, 0, s>>>(
+                C.n, P->cinv.p, vb(C), f, fstride, vx(C), xp);
+            R2P_LAUNCH();
+            return 0;
+        }
+        const Phys &ph = P->J->m->ph;
+        Level0<T> Z;
+        AmgLevel &A = P->lv[0];
+        Z.n = A.n; Z.nx = ph.nx; Z.nxy = ph.nx * ph.ny;
+        if constexpr (sizeof(T) == 4) Z.v7 = A.v7f.p; else Z.v7 = (const T *)A.v7.p;
+        Z.l1 = l1s(A);
+        Z.f = f;
+        Z.fstride = fstride;
+        k_down0<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(Z, vx(A), vxo(A));
+        R2P_LAUNCH();
+        R2P_TRY(restrict_to(0));
+        R2P_TRY(correct(0));
+        k_up0<T><<<r2p_blocks(Z.n, BS), BS, 0, s>>>(Z, vx(A), xp);
+        R2P_LAUNCH();
+        return 0;
+    }
+};
 
 int r2p_amg_cycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStream_t s) {
-    if (P->o.precision == R2P_FP32) return vcycle<float>(P, f, fstride, xp, s);
-    return vcycle<double>(P, f, fstride, xp, s);
+    if (P->o.precision == R2P_FP32) {
+        Cycle<float> c{P, s, P->nlev};
+        return c.run(f, fstride, xp);
+    }
+    Cycle<double> c{P, s, P->nlev};
+    return c.run(f, fstride, xp);
 }
 
 extern "C" int r2p_amg_info(r2p_cpr *P, int level, int *nlev, int *n, int *nnz) {

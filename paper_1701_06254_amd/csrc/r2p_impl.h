@@ -216,6 +216,8 @@ struct AmgLevel {
     AmgLevelT<float> f32;
     DBuf<double> b, x, xo;   // work vectors (fp64)
     DBuf<float> bf, xf, xof; // work vectors (fp32)
+    DBuf<double> kv;         // K-cycle level: p1, p2, q1, q2 (4n, fp64)
+    DBuf<float> kvf;         // the same in fp32
 };
 
 // Scratch of the set-up kept in the handle, so that repeated set-ups at the
@@ -224,14 +226,17 @@ struct AmgLevel {
 struct SetupWork {
     DBuf<unsigned> u[6];
     DBuf<int> i[4];
-    DBuf<double> d[1];
+    DBuf<double> d[2];
     DBuf<int> agg;                        // aggregates of the current pass
     DBuf<int> crp[2], ccol[2];            // intermediate Galerkin products
     DBuf<double> cval[2];
 };
 
+struct Krylov;
+
 struct r2p_cpr {
     r2p_cpr_opts o{};
+    Krylov *kry = nullptr;   // Krylov basis and work vectors of the solves with this handle
     SetupWork ws;
     r2p_jacobian *J = nullptr;
     int ready = 0;
@@ -244,6 +249,8 @@ struct r2p_cpr {
     DBuf<float> cinvf;
     DBuf<double> lu;         // coarsest dense LU scratch
     DBuf<int> piv;
+    DBuf<double> kscal;      // K-cycle scalars {q1.q1, a1, beta, a2} per level
+    DBuf<double> kpart;      // K-cycle dot-product partial sums
     DBuf<int> status;        // device status flags
     // level-0 structure cache, and the model the cached structures belong to
     int app_n = -1;
@@ -263,6 +270,10 @@ struct r2p_cpr {
     HostPinned apin;
     hipStream_t as = nullptr;            // non-blocking, default priority
     hipEvent_t aev[2] = {nullptr, nullptr};
+    // host wall times of the last set-up's stages (ms): decoupling; reordering
+    // (levels and local order); block ILU(0); AMG (on its own thread, beside
+    // the two before it)
+    double ms_dec = 0, ms_order = 0, ms_ras = 0, ms_amg = 0;
     ~r2p_cpr();
 };
 
@@ -282,6 +293,9 @@ int r2p_scan_int(const int *in, int *out, int n, int *total_host, DBuf<int> &tmp
                  HostPinned &pin, hipStream_t s);
 
 inline int r2p_blocks(long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// Host wall clock in ms (steady).
+double r2p_now_ms();
 
 // Compute units of the current device (cached per device).
 int r2p_cu_count();

@@ -972,6 +972,7 @@ __global__ void k_slice_meta(int nslice, const int *st, const int *cn, const int
 
 // ----------------------------------------------------------------- set-up
 int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
+    double t0 = r2p_now_ms();
     R2P_TRY(r2p_ras_static(P, s));
     r2p_jacobian *J = P->J;
     r2p_model *m = J->m;
@@ -1050,6 +1051,8 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
         R2P_LAUNCH();
         R2P_HIP(hipStreamSynchronize(s));
     }
+    double t1 = r2p_now_ms();
+    P->ms_order = t1 - t0;       // membership (when rebuilt), levels and the local order
     // 4. slices of 64 rows per level, entry bases
     k_slice_count<<<r2p_blocks(nseg + 1, BS), BS, 0, s>>>(nseg, D.lptr_dev.p, D.soff.p);
     R2P_LAUNCH();
@@ -1148,6 +1151,7 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     }
     R2P_HIP(hipMemcpyAsync(hflag, P->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
     R2P_HIP(hipStreamSynchronize(s));
+    P->ms_ras = r2p_now_ms() - t1;
     if (*hflag) { r2p_set_error("singular diagonal block in block ILU(0)"); return R2P_ESINGULAR; }
     D.maxlev = 0;
     for (int t = 0; t < ns; t++) D.maxlev = std::max(D.maxlev, D.h_nlev[t]);

@@ -273,6 +273,7 @@ extern "C" int r2p_cpr_destroy(r2p_cpr *P) {
 }
 
 r2p_cpr::~r2p_cpr() {
+    delete kry;
     for (hipEvent_t &e : aev)
         if (e) (void)hipEventDestroy(e);
     if (as) (void)hipStreamDestroy(as);
@@ -307,7 +308,9 @@ static int setup_both(r2p_cpr *P, hipStream_t s) {
             err_amg = "hipSetDevice failed on the AMG set-up thread";
             return;
         }
+        double ta = r2p_now_ms();
         rc_amg = r2p_amg_setup(P, P->as);
+        P->ms_amg = r2p_now_ms() - ta;
         if (rc_amg) err_amg = r2p_last_error();
     };
     std::thread t;
@@ -338,7 +341,7 @@ static int check_opts(const r2p_cpr_opts *o) {
         o->form > 1 || o->px < 1 || o->py < 1 || o->px * o->py > 256 || o->overlap < 0 ||
         o->overlap > 8 || !(o->theta >= 0) || o->max_coarse < 1 || o->max_coarse > 2048 ||
         o->max_levels < 1 || o->match_rounds < 1 || o->agg_passes < 1 || o->agg_passes > 4 ||
-        o->precision < 0 || o->precision > 1) {
+        o->precision < 0 || o->precision > 1 || o->kcycle < 0 || o->kcycle > 23) {
         r2p_set_error("invalid CPR options");
         return R2P_EINVAL;
     }
@@ -365,8 +368,13 @@ extern "C" int r2p_setup_cpr(r2p_jacobian *J, const r2p_cpr_opts *o, r2p_cpr *P,
     R2P_TRY(P->t_r.ensure(N));
     R2P_TRY(P->t_y.ensure(N));
     R2P_TRY(P->t_xp.ensure(ph.n));
+    P->ms_dec = P->ms_order = P->ms_ras = P->ms_amg = 0.0;
+    double t0 = r2p_now_ms();
     R2P_TRY(r2p_decouple_jacobian(J, o->decouple, s));
-    R2P_TRY(setup_both(P, s));
+    R2P_HIP(hipStreamSynchronize(s));
+    P->ms_dec = r2p_now_ms() - t0;
+    int rc = setup_both(P, s);
+    if (rc) return rc;          // errors, and the soft failure of a stalled coarsening
     P->ready = 1;
     return 0;
 }
@@ -390,11 +398,11 @@ extern "C" int r2p_ras_apply(r2p_cpr *P, const double *r, double *y, void *strea
 }
 
 // ---------------------------------------------------------------- FGMRES
+// The Krylov workspace belongs to the CPR handle (the Newton step's handle
+// belongs to its model) and is freed with it.
 static Krylov &krylov_for(r2p_cpr *P) {
-    static thread_local Krylov *K = nullptr;
-    (void)P;
-    if (!K) K = new Krylov();
-    return *K;
+    if (!P->kry) P->kry = new Krylov();
+    return *P->kry;
 }
 
 // Right-preconditioned BiCGSTAB on the decoupled system (the paper's other
@@ -623,6 +631,7 @@ extern "C" void r2p_default_newton_opts(r2p_newton_opts *o) {
     o->cpr.match_rounds = 4;
     o->cpr.agg_passes = 2;
     o->cpr.precision = R2P_FP64;
+    o->cpr.kcycle = 2;
     o->lin.restart = 30;
     o->lin.maxit = 300;
     o->lin.rtol = 1e-8;
@@ -643,9 +652,10 @@ struct NewtonWork {
 
 void r2p_newton_work_free(NewtonWork *W) { delete W; }
 
-static double now_ms() {
+double r2p_now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+static double now_ms() { return r2p_now_ms(); }
 
 // Newton iterations of Algorithm 1 from the iterate in W->xk (old state in
 // W->xold); status 0 when the scaled residual test passes.  Iteration counts
@@ -677,6 +687,14 @@ static int newton_loop(NewtonWork *W, Krylov &K, r2p_model *m, double dt,
         double ts = now_ms();
         rc = r2p_setup_cpr(W->J, &o->cpr, W->P, stream);
         inf.ms_setup += now_ms() - ts;
+        inf.ms_decouple += W->P->ms_dec;
+        inf.ms_order += W->P->ms_order;
+        inf.ms_ras_setup += W->P->ms_ras;
+        inf.ms_amg_setup += W->P->ms_amg;
+        inf.setup_status = rc;
+        // a failure of the method (stalled coarsening, a singular pivot) ends
+        // the step as not converged, so that the caller shortens it
+        if (rc > 0 || rc == R2P_ESINGULAR) break;
         if (rc) return rc;
         r2p_solve_opts lo = o->lin;
         if (o->forcing == R2P_FORCING_EW) lo.rtol = eta;
@@ -687,6 +705,7 @@ static int newton_loop(NewtonWork *W, Krylov &K, r2p_model *m, double dt,
         inf.linear_its += si.iterations;
         if (rc < 0) return rc;
         if (rc != 0 && o->forcing == R2P_FORCING_FIXED) break;
+        double tu = now_ms();
         if (o->forcing == R2P_FORCING_EW) {
             // ||b - J y|| of the undecoupled system (Eq 27)
             R2P_TRY(r2p_spmv_impl(W->J, W->y.p, W->t.p, K.bd.p, s));
@@ -698,6 +717,8 @@ static int newton_loop(NewtonWork *W, Krylov &K, r2p_model *m, double dt,
             prev_fn = fn;
         }
         R2P_TRY(r2p_newton_update(m, W->y.p, W->xk.p, o->ds_max, s));
+        R2P_HIP(hipStreamSynchronize(s));
+        inf.ms_update += now_ms() - tu;
         inf.newton_its++;
     }
     return 0;

@@ -45,7 +45,8 @@ class CprOpts(C.Structure):
     _fields_ = [("decouple", C.c_int), ("order", C.c_int), ("form", C.c_int),
                 ("px", C.c_int), ("py", C.c_int), ("overlap", C.c_int),
                 ("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int),
-                ("match_rounds", C.c_int), ("agg_passes", C.c_int), ("precision", C.c_int)]
+                ("match_rounds", C.c_int), ("agg_passes", C.c_int), ("precision", C.c_int),
+                ("kcycle", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -68,14 +69,17 @@ class NewtonInfo(C.Structure):
     _fields_ = [("status", C.c_int), ("newton_its", C.c_int), ("linear_its", C.c_int),
                 ("used_guess", C.c_int), ("res_hist", C.c_double * 32),
                 ("ms_assemble", C.c_double), ("ms_setup", C.c_double),
-                ("ms_solve", C.c_double), ("ms_total", C.c_double)]
+                ("ms_solve", C.c_double), ("ms_total", C.c_double),
+                ("ms_decouple", C.c_double), ("ms_order", C.c_double),
+                ("ms_ras_setup", C.c_double), ("ms_amg_setup", C.c_double),
+                ("ms_update", C.c_double), ("setup_status", C.c_int)]
 
 
 def cpr_opts(decouple=DEC_QI, order=ORDER_POTENTIAL, form=CPR_TWO_STAGE, px=4, py=4, overlap=1,
              theta=0.25, max_coarse=500, max_levels=20, match_rounds=4, agg_passes=2,
-             precision=FP64):
+             precision=FP64, kcycle=2):
     return CprOpts(decouple, order, form, px, py, overlap, theta, max_coarse, max_levels,
-                   match_rounds, agg_passes, precision)
+                   match_rounds, agg_passes, precision, kcycle)
 
 
 KRYLOV_FGMRES, KRYLOV_BICGSTAB = 0, 1
@@ -362,6 +366,13 @@ class Cpr:
         ns = C.c_int()
         _check(load().r2p_ras_info(self.h, -1, C.byref(ns), None, None, None))
         return ns.value
+
+    def ras_subdomain_info(self, s):
+        """(local rows, off-diagonal factor blocks, dependency levels) of subdomain s."""
+        ns, m, nb, nl = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        _check(load().r2p_ras_info(self.h, s, C.byref(ns), C.byref(m), C.byref(nb),
+                                   C.byref(nl)))
+        return m.value, nb.value, nl.value
 
     def ras_subdomain(self, s):
         L = load()

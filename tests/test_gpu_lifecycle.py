@@ -57,3 +57,28 @@ def test_one_cpr_handle_on_two_models(libs):
         assert info.status == 0 and info.relres <= 1e-8, w["name"]
         del J, m
         gc.collect()
+
+
+def test_model_destroy_releases_device_memory(libs):
+    """Each model's Newton workspace, including the Krylov basis of its CPR
+    handle, is freed with the model: after a 2M-cell step (about 2 GB of
+    FGMRES(30) basis) and the model's destruction, device memory in use
+    returns to its level before the model was created."""
+    import torch
+    r2p, _ = libs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, _ = torch.cuda.mem_get_info()
+    w = workloads.make_config(1)
+    m = r2p.Model(w)
+    x = m.initial_state()
+    info = m.newton_step(x, 0.1)
+    assert info.status == 0
+    free1, _ = torch.cuda.mem_get_info()
+    assert free0 - free1 > 2 * 2 ** 30               # the step's workspace was there
+    del m, x
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free2, _ = torch.cuda.mem_get_info()
+    assert free0 - free2 <= 64 * 2 ** 20, (free0 - free2) / 2 ** 20

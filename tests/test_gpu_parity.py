@@ -63,6 +63,17 @@ def _blocks(rp, col, val):
     return d
 
 
+def _assert_vec_close(g, o, rtol, nwell_rows=0):
+    """Element by element: every |g_i - o_i| <= rtol max|o|, the 2-norm of the
+    difference <= rtol ||o||, and the same on the well rows alone (the last
+    nwell_rows entries), whose values are of another scale."""
+    assert np.abs(g - o).max() <= rtol * np.abs(o).max()
+    assert np.linalg.norm(g - o) <= rtol * np.linalg.norm(o)
+    if nwell_rows:
+        gw, ow = g[-nwell_rows:], o[-nwell_rows:]
+        assert np.abs(gw - ow).max() <= rtol * max(np.abs(ow).max(), 1e-300)
+
+
 def _assert_blocks_close(dg, do, rtol, scale=None):
     assert set(dg) == set(do)
     if scale is None:
@@ -147,12 +158,19 @@ def test_decoupled_matrix_matches(dev, orc, dec):
     assert np.abs(val - Ad.val).max() <= 1e-12 * np.abs(Ad.val).max()
 
 
-def test_amg_hierarchy_matches(dev, orc):
+@pytest.mark.parametrize("max_coarse,kcycle", [(500, 2), (40, 0), (40, 2)])
+def test_amg_hierarchy_matches(dev, orc, max_coarse, kcycle):
+    """Hierarchy bit-exact in structure (aggregates, sparsity), values to
+    1e-12; one cycle (V-cycle, or the K-cycle on the kcycle finest levels)
+    element by element to 1e-10.  max_coarse 40 gives five levels, so the
+    K-cycle runs on two levels below the finest."""
     w = workloads.make_small()
-    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(dev, orc, w, 2, orc.cpr_opts(), dev.cpr_opts())
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
+        dev, orc, w, 2, orc.cpr_opts(max_coarse=max_coarse, kcycle=kcycle),
+        dev.cpr_opts(max_coarse=max_coarse, kcycle=kcycle))
     lo = Po.amg_levels()
     lg = P.amg_levels()
-    assert len(lo) == len(lg) >= 2
+    assert len(lo) == len(lg) >= (2 if max_coarse == 500 else 4)
     for a, g in zip(lo, lg):
         assert a["A"].n == g["n"]
         assert np.array_equal(a["A"].rp, g["rp"]) and np.array_equal(a["A"].col, g["col"])
@@ -161,12 +179,12 @@ def test_amg_hierarchy_matches(dev, orc):
         assert np.abs(a["l1"] - g["l1"]).max() <= 1e-12 * a["l1"].max()
         if a["agg"] is not None:
             assert np.array_equal(a["agg"], g["agg"])
-    # one V-cycle on a random right-hand side
     rng = np.random.default_rng(0)
-    f = rng.standard_normal(mo.n)
-    xg = _h(P.amg_vcycle(_t(f)))
-    xo = Po.amg_vcycle(f)
-    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+    for _ in range(2):
+        f = rng.standard_normal(mo.n)
+        xg = _h(P.amg_vcycle(_t(f)))
+        xo = Po.amg_vcycle(f)
+        _assert_vec_close(xg, xo, 1e-10)
 
 
 @pytest.mark.parametrize("order", [0, 1])
@@ -205,7 +223,7 @@ def test_ras_factors_match(dev, orc, order):
     r = rng.standard_normal(mo.N)
     yg = _h(P.ras_apply(_t(r)))
     yo = Po.ras_apply(r)
-    assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(yo)
+    _assert_vec_close(yg, yo, 1e-10, 2 * mo.nw)
 
 
 @pytest.mark.parametrize("form", [0, 1])
@@ -218,7 +236,7 @@ def test_cpr_apply_matches(dev, orc, form):
     f[2 * mo.n + 1::2] = 0.0
     zg = _h(P.apply(_t(f)))
     zo = Po.apply(f)
-    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+    _assert_vec_close(zg, zo, 1e-10, 2 * mo.nw)
 
 
 @pytest.mark.parametrize("form", [0, 1])
@@ -240,12 +258,13 @@ def test_fgmres_solve_matches(dev, orc, form):
 
 @pytest.mark.parametrize("form", [0, 1])
 def test_bicgstab_solve_matches(dev, orc, form):
-    """BiCGSTAB (two CPR applications per iteration) on the same system: the
-    true relative residual of the device solution at most 1e-8, and the
-    iteration count within 2 of the oracle's."""
+    """BiCGSTAB (two CPR applications per iteration) on the same system, with
+    the V-cycle as the pressure stage (BiCGSTAB needs a fixed
+    preconditioner): the true relative residual of the device solution at
+    most 1e-8, and the iteration count within 2 of the oracle's."""
     w = workloads.make_small()
     mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
-        dev, orc, w, 3, orc.cpr_opts(form=form), dev.cpr_opts(form=form))
+        dev, orc, w, 3, orc.cpr_opts(form=form, kcycle=0), dev.cpr_opts(form=form, kcycle=0))
     yo, st, its_o, rr_o = orc.bicgstab(Ad, bd, Po)
     assert st == 0
     yg, info = dev.solve(J, P, b, dev.solve_opts(method=dev.KRYLOV_BICGSTAB))
@@ -358,11 +377,11 @@ def test_many_subdomains_match(dev, orc, tiles):
     rng = np.random.default_rng(8)
     r = rng.standard_normal(mo.N)
     yg, yo = _h(P.ras_apply(_t(r))), Po.ras_apply(r)
-    assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(yo)
+    _assert_vec_close(yg, yo, 1e-10, 2 * mo.nw)
     f = rng.standard_normal(mo.N)
     f[2 * mo.n + 1::2] = 0.0
     zg, zo = _h(P.apply(_t(f))), Po.apply(f)
-    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+    _assert_vec_close(zg, zo, 1e-10, 2 * mo.nw)
 
 
 def test_cpr_apply_overlap2_matches(dev, orc):
@@ -375,4 +394,4 @@ def test_cpr_apply_overlap2_matches(dev, orc):
     f[2 * mo.n + 1::2] = 0.0
     zg = _h(P.apply(_t(f)))
     zo = Po.apply(f)
-    assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+    _assert_vec_close(zg, zo, 1e-10, 2 * mo.nw)

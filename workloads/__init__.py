@@ -267,6 +267,36 @@ def random_state(w, rng, p_spread=50.0, tie_free=False):
     return x
 
 
+def developed_state(w, x0, rng, p_mound=300.0, length=15.0, radius=10.0):
+    """A state shaped like one some days into the run, from a base state x0
+    (the hydrostatic start, length 2*(n + nw)): a pressure mound of
+    `p_mound` psi around every injector and a sink of the same depth around
+    every producer (exp(-r/length), r in cells), and a water plume around
+    every injector whose radius varies per layer (s_w = 0.8 (1 - r/R_k)
+    inside R_k = radius * U(0.3, 1.5)).  Geometry and seeded noise only.
+    """
+    g = w["grid"]
+    nx, ny, nz, n = g["nx"], g["ny"], g["nz"], g["n"]
+    x = np.array(x0, dtype=np.float64, copy=True)
+    c = np.arange(n)
+    ci, cj, ck = c % nx, (c // nx) % ny, c // (nx * ny)
+    dp = np.zeros(n)
+    sw = np.zeros(n)
+    for wl in w["wells"]:
+        i0, j0 = wl["cells"][0] % nx, (wl["cells"][0] // nx) % ny
+        r = np.hypot(ci - i0, cj - j0)
+        sign = 1.0 if wl["kind"] == INJ else -1.0
+        dp += sign * p_mound * np.exp(-r / length)
+        if wl["kind"] == INJ:
+            R = radius * rng.uniform(0.3, 1.5, nz)[ck]
+            sw = np.maximum(sw, 0.8 * np.clip(1.0 - r / R, 0.0, 1.0))
+    x[0:2 * n:2] += dp
+    x[1:2 * n:2] = sw
+    for k, wl in enumerate(w["wells"]):
+        x[2 * (n + k)] += dp[wl["cells"][0]]
+    return x
+
+
 def flat_wells(w):
     """Wells as flat arrays: ptr[nw+1], cells, kind, ctrl, target, rw, skin."""
     wells = w["wells"]
