@@ -203,6 +203,18 @@ int r2p_assemble_jacobian(r2p_model *m, const double *x, const double *x_old, do
  * Synchronises `stream`.  NaN in b gives R2P_ENAN. */
 int r2p_residual_norm(r2p_model *m, const double *b, double dt, double *norm_host, void *stream);
 
+/* The same scaled norm for callers that cannot allocate device or pinned
+ * memory (code under HIP graph capture, tight serving loops): asynchronous
+ * on `stream`, it writes the norm (NaN if a residual entry is not finite)
+ * into norm_dev, a device double owned by the caller, and allocates nothing.
+ * Its per-workgroup partial maxima live in a library scratch array of
+ * 4 MiB per GPU, held until the process ends: n + nw may be at most 2^26
+ * (R2P_EINVAL beyond).  Calls that overlap on one GPU (other streams or
+ * threads) share that array and race; the result equals r2p_residual_norm
+ * bit for bit. */
+int r2p_residual_norm_noalloc(r2p_model *m, const double *b, double dt, double *norm_dev,
+                              void *stream);
+
 /* y[N] <- J x[N] with J as currently stored (decoupled once set up). */
 int r2p_spmv(r2p_jacobian *J, const double *x, double *y, void *stream);
 

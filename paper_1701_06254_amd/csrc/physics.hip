@@ -16,10 +16,13 @@
 // and flux arithmetic (and with it every upstream decision) is reproducible.
 #include <atomic>
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 
 #include "r2p_impl.h"
+
+int r2p_noalloc_init(int dev);
 
 constexpr int BS = 256;
 
@@ -121,6 +124,7 @@ extern "C" int r2p_model_create(const r2p_model_desc *d, r2p_model **out) {
         }
     }
     R2P_HIP(hipSetDevice(d->device));
+    R2P_TRY(r2p_noalloc_init(d->device));
     r2p_model *m = new r2p_model();
     static std::atomic<unsigned long long> next_serial{1};
     m->serial = next_serial++;
@@ -543,6 +547,118 @@ extern "C" int r2p_residual_norm(r2p_model *m, const double *b, double dt, doubl
     memcpy(&v, &h[0], sizeof(double));
     *norm = v;
     if (h[1]) { *norm = NAN; r2p_set_error("non-finite residual"); return R2P_ENAN; }
+    return 0;
+}
+
+// ----------------------------------------------- allocation-free scaled norm
+// For callers that cannot allocate (HIP graph capture, serving loops): the
+// per-workgroup partial maxima live in a file-scope device array, one copy
+// per GPU, whose address each device resolves once (at model creation, with
+// that device current).  Host code uses only that resolved address.
+constexpr int NOALLOC_BLOCKS = 1 << 18;     // workgroups of BS rows: at most 2^26 rows
+static __device__ __align__(256) unsigned long long scratch[2 * NOALLOC_BLOCKS];
+constexpr int NOALLOC_MAX_DEV = 64;
+static unsigned long long *noalloc_ptr[NOALLOC_MAX_DEV];
+static std::mutex noalloc_mu;
+
+int r2p_noalloc_init(int dev) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV) { r2p_set_error("device ordinal %d out of range", dev); return R2P_EINVAL; }
+    std::lock_guard<std::mutex> g(noalloc_mu);
+    if (noalloc_ptr[dev]) return 0;
+    void *ptr = nullptr;
+    R2P_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    noalloc_ptr[dev] = (unsigned long long *)ptr;
+    return 0;
+}
+
+// Partial maxima of the scaled residual (the same per-row values as
+// k_resnorm) per workgroup: part[blk] = the largest as bits, part[nb + blk]
+// = 1 if a row was not finite.  Every entry is written, so nothing needs
+// clearing between calls.
+__global__ void k_resnorm_part(Phys P, const double *phi, const double *w_target, const double *b,
+                               double dt, unsigned long long *part) {
+    __shared__ unsigned long long smax[BS / 64];
+    __shared__ int snan[BS / 64];
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    double v = 0.0;
+    int nan = 0;
+    if (i < P.n) {
+        double pv = P.dx * P.dy * P.dz * phi[i] / P.alpha;
+        double a = fabs(b[2 * i]) * dt / pv, c = fabs(b[2 * i + 1]) * dt / pv;
+        nan = (a != a) || (c != c);
+        v = a > c ? a : c;
+    } else if (i < P.n + P.nw) {
+        int w = (int)(i - P.n);
+        double t = fabs(w_target[w]);
+        v = fabs(b[2 * i]) / (t > 0.0 ? t : 1.0);
+        nan = v != v;
+    }
+    unsigned long long u = nan ? 0ull : (unsigned long long)__double_as_longlong(v);
+    for (int d = 32; d > 0; d >>= 1) {
+        unsigned long long o = __shfl_xor(u, d, 64);
+        u = o > u ? o : u;
+        nan |= __shfl_xor(nan, d, 64);
+    }
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { smax[wid] = u; snan[wid] = nan; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long mx = 0;
+        int nn = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) { mx = smax[w] > mx ? smax[w] : mx; nn |= snan[w]; }
+        part[blockIdx.x] = mx;
+        part[gridDim.x + blockIdx.x] = (unsigned long long)nn;
+    }
+}
+
+// norm = the largest partial, or NaN if any row was not finite.
+__global__ __launch_bounds__(1024) void k_resnorm_fin(int nb, const unsigned long long *part,
+                                                      double *norm) {
+    __shared__ unsigned long long smax[1024 / 64];
+    __shared__ int snan[1024 / 64];
+    unsigned long long mx = 0;
+    int nan = 0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        unsigned long long v = part[k];
+        mx = v > mx ? v : mx;
+        nan |= part[nb + k] != 0;
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        unsigned long long o = __shfl_xor(mx, d, 64);
+        mx = o > mx ? o : mx;
+        nan |= __shfl_xor(nan, d, 64);
+    }
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { smax[wid] = mx; snan[wid] = nan; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = 0;
+        int nn = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) { m = smax[w] > m ? smax[w] : m; nn |= snan[w]; }
+        *norm = nn ? __longlong_as_double(0x7ff8000000000000ll) : __longlong_as_double((long long)m);
+    }
+}
+
+extern "C" int r2p_residual_norm_noalloc(r2p_model *m, const double *b, double dt, double *norm,
+                                         void *stream) {
+    if (!m || !b || !norm) { r2p_set_error("NULL argument"); return R2P_EINVAL; }
+    long tot = (long)m->ph.n + m->ph.nw;
+    long nb = (tot + BS - 1) / BS;
+    if (nb > NOALLOC_BLOCKS) {
+        r2p_set_error("r2p_residual_norm_noalloc: %ld rows exceed its scratch limit of %ld rows",
+                      tot, (long)NOALLOC_BLOCKS * BS);
+        return R2P_EINVAL;
+    }
+    if (m->dev < 0 || m->dev >= NOALLOC_MAX_DEV || !noalloc_ptr[m->dev]) {
+        r2p_set_error("scratch of device %d not resolved", m->dev);
+        return R2P_ESTATE;
+    }
+    unsigned long long *part = noalloc_ptr[m->dev];
+    hipStream_t s = (hipStream_t)stream;
+    k_resnorm_part<<<(int)nb, BS, 0, s>>>(m->ph, m->phi.p, m->w_target.p, b, dt, part);
+    R2P_LAUNCH();
+    k_resnorm_fin<<<1, 1024, 0, s>>>((int)nb, part, norm);
+    R2P_LAUNCH();
     return 0;
 }
 

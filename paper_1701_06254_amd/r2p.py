@@ -100,7 +100,7 @@ def newton_opts(max_newton=20, tol=1e-8, forcing=FORCING_FIXED, ds_max=0.2, cpr=
 
 EXPORTS = ["r2p_model_create", "r2p_model_destroy", "r2p_model_sizes", "r2p_initial_state",
            "r2p_jacobian_create", "r2p_jacobian_destroy", "r2p_assemble_jacobian",
-           "r2p_residual_norm", "r2p_spmv", "r2p_jacobian_export", "r2p_cpr_create",
+           "r2p_residual_norm", "r2p_residual_norm_noalloc", "r2p_spmv", "r2p_jacobian_export", "r2p_cpr_create",
            "r2p_cpr_destroy", "r2p_setup_cpr", "r2p_cpr_apply", "r2p_amg_vcycle",
            "r2p_ras_apply", "r2p_amg_info", "r2p_amg_export_level", "r2p_ras_info",
            "r2p_ras_export", "r2p_solve", "r2p_newton_step", "r2p_default_newton_opts",
@@ -128,6 +128,7 @@ def load(path=LIB_PATH):
         "r2p_jacobian_destroy": [vp],
         "r2p_assemble_jacobian": [vp, vp, vp, C.c_double, vp, vp, vp],
         "r2p_residual_norm": [vp, vp, C.c_double, dp, vp],
+        "r2p_residual_norm_noalloc": [vp, vp, C.c_double, vp, vp],
         "r2p_spmv": [vp, vp, vp, vp],
         "r2p_jacobian_export": [vp, ip, vp, vp, vp, vp],
         "r2p_cpr_create": [C.POINTER(vp)],
@@ -250,6 +251,11 @@ class Model:
             return float("nan")
         _check(rc)
         return v.value
+
+    def residual_norm_noalloc(self, b, dt, out):
+        """Scaled norm into the device double `out` (asynchronous; no allocation)."""
+        _check(load().r2p_residual_norm_noalloc(self.h, _ptr(b), float(dt), _ptr(out), _stream()))
+        return out
 
     def newton_step(self, x, dt, opts=None, x_guess=None):
         """One implicit step on x in place; returns the NewtonInfo record."""
