@@ -49,7 +49,7 @@ HBM_PEAK_GBS = 8000.0
 # 512 MiB device copy, so FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0.
 # Valid only for the RAS source these were taken on (first 16 hex digits of
 # its SHA-256); any change to it reports traffic as null.
-RAS_TRAFFIC = {"source_sha256": "4df35a771ea3cf53",
+RAS_TRAFFIC = {"source_sha256": "cdeaaad899b7cde9",
                "fetch_kib": 26518.0 + 366158.3 + 21394.8, "fetch_scale": 2.0,
                "write_kib": 41605.2 + 65658.1 + 62616.9, "write_scale": 1.0}
 DT_INIT, DT_MIN = 0.1, 1e-4
@@ -215,12 +215,15 @@ def newton_record(info, dt):
 
 def run_steps(model, x, dt, nsteps, opts, dt_max, tag, dts=None):
     """nsteps accepted implicit steps on x (in place).  With `dts` given the
-    step lengths are replayed instead of controlled.  Returns the next step
-    length and one record per attempted Newton step."""
+    step lengths are replayed instead of controlled: a replayed step whose
+    Newton iteration fails is covered by halved sub-steps, so the replay
+    reaches the same simulated time.  Returns the next step length and one
+    record per attempted Newton step."""
     recs = []
     for k in range(nsteps):
+        remaining = dts[k] if dts is not None else None
         if dts is not None:
-            dt = dts[k]
+            dt = remaining
         while True:
             info = model.newton_step(x, dt, opts)
             recs.append(newton_record(info, dt))
@@ -228,7 +231,13 @@ def run_steps(model, x, dt, nsteps, opts, dt_max, tag, dts=None):
                 f"linear {info.linear_its} setup {info.ms_setup:.0f} solve {info.ms_solve:.0f} "
                 f"total {info.ms_total:.0f} ms")
             if info.status == 0:
-                break
+                if dts is None:
+                    break
+                remaining -= dt
+                if remaining <= 1e-9 * dts[k]:
+                    break
+                dt = min(dt, remaining)
+                continue
             dt *= 0.5
             if dt < DT_MIN:
                 raise RuntimeError("time step fell below the minimum")
@@ -275,34 +284,35 @@ def learned_run(args, model, x0, x64, dts, form, log):
     """FP32 preconditioner plus the learned warm start on the same steps.
 
     The network is trained first (not timed) on increments of seeded
-    80x80x50 models of the same family (correlated field, wells 40 cells
-    apart, 4,000 STB/d injectors, 4,000 psi producers), each run from its cold
-    start by the same step-length controller as the timed run (0.1, 0.1,
-    0.2, 0.4, 0.8 days).  Each timed step evaluates the scaled residual at
-    the network's iterate and at x^n and starts Newton from the smaller (the
-    library's default rule); the two norms are reported per step."""
+    200x200x50 models of the workload's family with new permeability fields
+    (seeds 1000 + i; the timed workload is seed 1, held out), each run from
+    its cold start through the same step-length controller as the timed run,
+    every accepted step kept as four random 48x48-column crops over all
+    layers (the recipe of paper_1701_06254_amd.learned_study at a smaller
+    count).  Each timed step evaluates the scaled residual at the network's
+    iterate and at x^n and starts Newton from the smaller (the library's
+    default rule); the two norms are reported per step."""
     import numpy as np
     import torch
-    import workloads
-    from paper_1701_06254_amd import r2p, warmstart
+    from paper_1701_06254_amd import r2p, warmstart, learned_study
     o64 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form))
     t0 = time.perf_counter()
-    pairs = []
-    for seed in range(1001, 1001 + args.train_models):
-        w = workloads.make_gaussian(nx=80, ny=80, nz=50, seed=seed, well_pattern=2)
-        m = r2p.Model(w)
-        xs = m.initial_state()
-        warmstart.collect_pairs(m, xs, [0.1, 0.1, 0.2, 0.4, 0.8], o64, pairs)
+    rng = np.random.default_rng(2024)
+    pairs = learned_study.collect(range(1000, 1000 + args.train_models), args.train_steps,
+                                  4, o64, rng)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     net = r2p.Cnn(blocks=4)
     net.set_params(warmstart.init_params(np.random.default_rng(7)))
-    losses = warmstart.train(net, pairs, (50, 80, 80), args.train_iters, batch=2, lr=1e-3,
-                             seed=3, log=log)
+    losses = warmstart.train(net, pairs, (50, learned_study.CROP, learned_study.CROP),
+                             args.train_iters, batch=4, lr=1e-3, seed=3, log=log)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    log(f"learned start: {len(pairs)} pairs in {t1 - t0:.1f} s, {args.train_iters} Adam steps "
-        f"in {t2 - t1:.1f} s, loss {np.mean(losses[:20]):.3e} -> {np.mean(losses[-20:]):.3e}")
+    del pairs
+    torch.cuda.empty_cache()
+    log(f"learned start: {args.train_models} training runs in {t1 - t0:.1f} s, "
+        f"{args.train_iters} Adam steps in {t2 - t1:.1f} s, loss {np.mean(losses[:20]):.3e} -> "
+        f"{np.mean(losses[-20:]):.3e}")
     # inference throughput on the full grid (algorithmic flops of the
     # unpadded layers: 6->32, 8 x 32->32, 32->2, 3x3x3 taps)
     feat = r2p.cnn_features(model, x0, dts[0])
@@ -355,7 +365,8 @@ def learned_run(args, model, x0, x64, dts, form, log):
                 rel_err_p=float(torch.linalg.norm(pl - p64) / torch.linalg.norm(p64)),
                 rel_err_sw=float(torch.linalg.norm(sl - s64) /
                                  max(float(torch.linalg.norm(s64)), 1e-300)),
-                training={"models": args.train_models, "pairs": len(pairs),
+                training={"runs": args.train_models, "grid": "200x200x50",
+                          "crop": [50, learned_study.CROP, learned_study.CROP],
                           "adam_steps": args.train_iters, "data_s": round(t1 - t0, 2),
                           "train_s": round(t2 - t1, 2),
                           "loss_first20": float(np.mean(losses[:20])),
@@ -447,7 +458,7 @@ def large_run(args, w, log):
 
     t1 = time.perf_counter()
     pairs = []
-    for seed in range(2001, 2001 + args.train_models):
+    for seed in range(2001, 2001 + 16):
         wt = workloads.make_channels(nx=80, ny=80, nz=40, seed=seed, n_channels=4,
                                      well_pattern=2)
         mt = r2p.Model(wt)
@@ -493,7 +504,7 @@ def large_run(args, w, log):
             "rel_err_p": float(torch.linalg.norm(pl - p64) / torch.linalg.norm(p64)),
             "rel_err_sw": float(torch.linalg.norm(s_l - s_64) /
                                 max(float(torch.linalg.norm(s_64)), 1e-300)),
-            "training": {"models": args.train_models, "adam_steps": args.train_iters,
+            "training": {"models": 16, "adam_steps": args.train_iters,
                          "seconds": round(train_s, 1),
                          "loss_first20": float(np.mean(losses[:20])),
                          "loss_last20": float(np.mean(losses[-20:]))}}
@@ -572,8 +583,11 @@ def main():
                     help="skip the method variants on the last system and the EW-forcing replay")
     ap.add_argument("--budget-s", type=float, default=420.0,
                     help="optional legs that would start after this many seconds are skipped")
-    ap.add_argument("--train-models", type=int, default=16,
-                    help="seeded 80x80x50 models of the same family that give training pairs")
+    ap.add_argument("--train-models", type=int, default=3,
+                    help="seeded 200x200x50 runs of the same family (new permeability fields) "
+                         "that give training pairs")
+    ap.add_argument("--train-steps", type=int, default=8,
+                    help="controller steps per training run")
     ap.add_argument("--train-iters", type=int, default=1500)
     ap.add_argument("--kernels-only", action="store_true",
                     help="for hardware-counter runs: set up the first Newton system of the "
@@ -738,6 +752,20 @@ def main():
     out["snapshot_solves"] = leg("snapshots", lambda: snapshot_solves(
         model, [("cold start", x_init), (f"after {args.warmup} warm-up steps", x0),
                 (f"after {args.warmup + args.steps} steps", x)], dt_max, form, log))
+
+    # ---- why the controller stays below 10 days: one 10-day step from the
+    # states the snapshots use
+    def ten_day_leg():
+        res = []
+        for name, xs in (("cold start", x_init), (f"after {args.warmup + args.steps} steps", x)):
+            xt = xs.clone()
+            info = model.newton_step(xt, dt_max, o64)
+            res.append({"state": name, "dt_days": dt_max, "status": info.status,
+                        "newton_its": info.newton_its, "linear_its": info.linear_its,
+                        "last_scaled_residual": info.res_hist[min(info.newton_its, 31)]})
+        log(f"10-day attempts: {res}")
+        return res
+    out["ten_day_step_attempts"] = leg("ten_day", ten_day_leg)
 
     # ---- the oracle on the host
     def cpu_leg():

@@ -158,6 +158,51 @@ def backward(theta, acts, out, target, C=32, K=4):
     return np.concatenate(parts)
 
 
+def forward_bf16(theta, f, C=32, K=4):
+    """The network with activations stored in bfloat16, as the extension
+    specifies (BF16 weights and activations, FP32 accumulation): every
+    hidden layer's result, after its bias, residual addend and ReLU, is
+    rounded to the nearest bfloat16; the output layer is not.  Sums are in
+    FP64 here, so each rounding sees its exact argument."""
+    P = unpack(theta, C, K)
+    h = bf16_round(relu(conv(f, *P["in"])))
+    acts = {"f": f, "h0": h}
+    for k in range(K):
+        a = bf16_round(relu(conv(h, *P[f"a{k}"])))
+        h = bf16_round(conv(a, *P[f"b{k}"]) + h)
+        acts[f"a{k}"] = a
+        acts[f"h{k + 1}"] = h
+    out = conv(h, *P["out"])
+    return out, acts
+
+
+def backward_bf16(theta, acts, out, target, C=32, K=4):
+    """Gradient of the mean squared error with the back-propagated signals
+    stored in bfloat16 like the activations: the output gradient, and after
+    every transposed convolution (with its ReLU mask or residual addend) the
+    input gradient; weight and bias gradients are sums of products of those
+    bfloat16 values, not rounded."""
+    P = unpack(theta, C, K)
+    grads = {}
+    g = bf16_round(2.0 * (out - target) / out.size)
+    grads["out"] = conv_grad_weight(g, acts[f"h{K}"])
+    gh = bf16_round(conv_grad_input(g, P["out"][0]))
+    for k in reversed(range(K)):
+        a, h = acts[f"a{k}"], acts[f"h{k}"]
+        grads[f"b{k}"] = conv_grad_weight(gh, a)
+        ga = bf16_round(conv_grad_input(gh, P[f"b{k}"][0]) * (a > 0))
+        grads[f"a{k}"] = conv_grad_weight(ga, h)
+        gh = bf16_round(gh + conv_grad_input(ga, P[f"a{k}"][0]))
+    g0 = gh * (acts["h0"] > 0)
+    grads["in"] = conv_grad_weight(g0, acts["f"])
+    parts = []
+    for name, _, _ in layer_shapes(C, K):
+        dW, db = grads[name]
+        parts.append(dW.ravel())
+        parts.append(db.ravel())
+    return np.concatenate(parts)
+
+
 def bf16_round(x):
     """Round to the nearest bfloat16 (ties to even), returned as float64."""
     a = np.asarray(x, dtype=np.float32)

@@ -25,6 +25,8 @@
 #include "r2p_impl.h"
 
 constexpr int BS = 256;
+constexpr int G = 4;                // lanes per row of the coarse-level row kernels
+constexpr int KO_BLOCKS = 1024;     // grid of the K-cycle orthogonalisation pass
 
 // ------------------------------------------------------- level 0 = A_pp
 __global__ void k_app_count(Phys P, int *cnt) {
@@ -329,10 +331,8 @@ __global__ void k_to_dense(int n, const int *rp, const int *col, const double *v
 }
 
 // LU with partial pivoting (largest magnitude, ties to the smaller row) by
-// one workgroup, then the inverse column by column; the inverse is written
-// column-major so the coarse solve reads it coalesced.
-__global__ __launch_bounds__(1024) void k_dense_lu_inv(int n, double *a, int *piv, double *invT,
-                                                     int *status) {
+// one workgroup, in place (unit L below the diagonal, U on and above).
+__global__ __launch_bounds__(1024) void k_dense_lu(int n, double *a, int *piv, int *status) {
     __shared__ double sv[1024];
     __shared__ int si[1024];
     int tid = threadIdx.x, nt = blockDim.x;
@@ -380,40 +380,48 @@ __global__ __launch_bounds__(1024) void k_dense_lu_inv(int n, double *a, int *pi
         }
         __syncthreads();
     }
-    // inverse: column c of A^-1 solves A x = e_c, one thread per column.
-    // While they are solved the columns sit interleaved, x_c[i] at
-    // invT[i*n + c], so a wavefront's accesses are contiguous; the matrix is
-    // then transposed in place to invT[c*n + i].
-    for (int c = tid; c < n; c += nt) {
-        for (int i = 0; i < n; i++) invT[(long)i * n + c] = i == c ? 1.0 : 0.0;
+}
+
+// Column c of the inverse from the LU factors, one wavefront per column:
+// x = P e_c, then the unit-lower and upper triangular solves, each row's
+// inner product split over the lanes (row i of the factors is read by every
+// column's wavefront, so it is served from L2) and summed by a fixed
+// butterfly.  Written column-major, invT[c*n + i] = (A^-1)_ic, so the
+// coarse solve reads it coalesced.
+__global__ __launch_bounds__(64) void k_dense_inv_col(int n, const double *a, const int *piv,
+                                                      const int *status, double *invT) {
+    extern __shared__ double xs[];
+    if (*status) return;             // singular: the factors are incomplete
+    int c = blockIdx.x, lane = threadIdx.x;
+    for (int i = lane; i < n; i += 64) xs[i] = i == c ? 1.0 : 0.0;
+    __syncthreads();
+    if (lane == 0)
         for (int k = 0; k < n; k++) {
             int p = piv[k];
-            if (p != k) {
-                double t = invT[(long)k * n + c];
-                invT[(long)k * n + c] = invT[(long)p * n + c];
-                invT[(long)p * n + c] = t;
+            if (p != k && p >= 0 && p < n) {
+                double t = xs[k];
+                xs[k] = xs[p];
+                xs[p] = t;
             }
         }
-        for (int i = 0; i < n; i++) {
-            double s = invT[(long)i * n + c];
-            for (int j = 0; j < i; j++) s -= a[(long)i * n + j] * invT[(long)j * n + c];
-            invT[(long)i * n + c] = s;
-        }
-        for (int i = n - 1; i >= 0; i--) {
-            double s = invT[(long)i * n + c];
-            for (int j = i + 1; j < n; j++) s -= a[(long)i * n + j] * invT[(long)j * n + c];
-            invT[(long)i * n + c] = s / a[(long)i * n + i];
-        }
-    }
     __syncthreads();
-    for (long t = tid; t < (long)n * n; t += nt) {
-        int i = (int)(t / n), j = (int)(t % n);
-        if (i < j) {
-            double u = invT[(long)i * n + j];
-            invT[(long)i * n + j] = invT[(long)j * n + i];
-            invT[(long)j * n + i] = u;
-        }
+    for (int i = 1; i < n; i++) {
+        double s = 0.0;
+        for (int j = lane; j < i; j += 64) s += a[(long)i * n + j] * xs[j];
+        for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+        __syncthreads();
+        if (lane == 0) xs[i] -= s;
+        __syncthreads();
     }
+    for (int i = n - 1; i >= 0; i--) {
+        double s = 0.0;
+        for (int j = i + 1 + lane; j < n; j += 64) s += a[(long)i * n + j] * xs[j];
+        for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+        __syncthreads();
+        if (lane == 0) xs[i] = (xs[i] - s) / a[(long)i * n + i];
+        __syncthreads();
+    }
+    for (int i = lane; i < n; i += 64) invT[(long)c * n + i] = xs[i];
 }
 
 // --------------------------------------------------------------- set-up
@@ -633,10 +641,13 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
         if (k >= 1 && k <= P->o.kcycle && k < P->nlev - 1) {
             if (f32) R2P_TRY(A.kvf.ensure(4L * A.n));
             else R2P_TRY(A.kv.ensure(4L * A.n));
+            // partial pairs of the K-cycle products on this level (and of the
+            // orthogonalisation pass, KO_BLOCKS at most)
+            long nbk = r2p_blocks(A.n, BS / G) + r2p_blocks(A.nheavy, BS / 64);
+            R2P_TRY(P->kpart.ensure(2 * std::max(nbk, (long)KO_BLOCKS)));
         }
     }
     R2P_TRY(P->kscal.ensure(4 * 24));
-    R2P_TRY(P->kpart.ensure(2 * 256));
     // coarsest level: dense LU and inverse (FP64)
     AmgLevel &C = P->lv[P->nlev - 1];
     int nc = C.n;
@@ -654,7 +665,10 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
     R2P_HIP(hipMemsetAsync(P->astatus.p, 0, sizeof(int), s));
     k_to_dense<<<r2p_blocks(nc, BS), BS, 0, s>>>(nc, C.rp.p, C.col.p, C.val.p, P->lu.p);
     R2P_LAUNCH();
-    k_dense_lu_inv<<<1, 1024, 0, s>>>(nc, P->lu.p, P->piv.p, P->cinv.p, P->astatus.p);
+    k_dense_lu<<<1, 1024, 0, s>>>(nc, P->lu.p, P->piv.p, P->astatus.p);
+    R2P_LAUNCH();
+    k_dense_inv_col<<<nc, 64, sizeof(double) * nc, s>>>(nc, P->lu.p, P->piv.p, P->astatus.p,
+                                                          P->cinv.p);
     R2P_LAUNCH();
     int *h = (int *)P->apin.p;
     R2P_HIP(hipMemcpyAsync(h, P->astatus.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -673,7 +687,6 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s) {
 // row reads is formed beforehand: the pre-smoothed x = b / d by the
 // restriction that produces b, and the prolonged x + P xc by a pass over the
 // fine rows, so each entry costs one gather.
-constexpr int G = 4;
 
 template <class T>
 struct CsrArgs {
@@ -872,19 +885,15 @@ __global__ __launch_bounds__(64 * CS_WAVES) void k_coarse_solve(int n, const dou
 // a1 = (q1.b)/(q1.q1), r = b - a1 q1; p2 = C(r), q2 = A p2,
 // beta = (q1.q2)/(q1.q1), p2 -= beta p1, q2 -= beta q1, a2 = (q2.r)/(q2.q2);
 // the correction a1 p1 + a2 p2 is added by the prolongation.  The scalars
-// stay on the device: each group of dot products is summed per workgroup,
-// then in workgroup order by one workgroup that also forms the scalar, so
-// nothing is read back and the sums do not depend on scheduling.
-constexpr int KD_BLOCKS = 256;
-template <class T>
-__global__ __launch_bounds__(BS) void k_kdots(int n, const T *a0, const T *b0, const T *a1,
-                                              const T *b1, double *part) {
+// stay on the device: the kernels that produce q1, q2 and the orthogonalised
+// q2 also write per-workgroup partial sums of the dot products they feed,
+// and one small workgroup adds the partials in workgroup order and forms
+// the scalar, so nothing is read back and the sums do not depend on
+// scheduling.
+
+// Workgroup sum of (s0, s1) into part[blockIdx.x], part[gridDim.x + blockIdx.x].
+__device__ __forceinline__ void block_partials(double s0, double s1, double *part) {
     __shared__ double red[2][BS / 64];
-    double s0 = 0.0, s1 = 0.0;
-    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) {
-        s0 += (double)a0[i] * (double)b0[i];
-        if (a1) s1 += (double)a1[i] * (double)b1[i];
-    }
     for (int d = 32; d > 0; d >>= 1) {
         s0 += __shfl_xor(s0, d, 64);
         s1 += __shfl_xor(s1, d, 64);
@@ -900,12 +909,73 @@ __global__ __launch_bounds__(BS) void k_kdots(int n, const T *a0, const T *b0, c
     }
 }
 
-// ks = {q1.q1, a1, beta, a2}.  step 0: from (q1.q1, q1.b); 1: from q1.q2;
-// 2: from (q2.q2, q2.r).  A zero denominator gives a zero step.
-__global__ __launch_bounds__(BS) void k_kfin(int nb, const double *part, int step, double *ks) {
-    __shared__ double red[2][BS / 64];
+// q = A p on a CSR level with the launch shape of k_csr_level (rows by
+// groups of G lanes, rows longer than HEAVY by a wavefront in trailing
+// workgroups), with per-workgroup partial dot products of q:
+// DOT 0: (q.q, q.b); DOT 1: (q1.q, 0).
+template <class T, int DOT>
+__global__ __launch_bounds__(BS) void k_kspmv(CsrArgs<T> A, const T *q1, double *part) {
     double s0 = 0.0, s1 = 0.0;
-    for (int b = threadIdx.x; b < nb; b += BS) { s0 += part[b]; s1 += part[nb + b]; }
+    if ((int)blockIdx.x < A.nbs) {
+        int i = xcd_block(blockIdx.x, A.nbs) * (BS / G) + (int)threadIdx.x / G;
+        int lane0 = threadIdx.x % G;
+        bool valid = i < A.n;
+        int z0 = valid ? A.rp[i] : 0, z1 = valid ? A.rp[i + 1] : 0;
+        bool heavy = z1 - z0 > HEAVY;
+        T acc = (T)0;
+        if (!heavy) {
+            for (int z = z0 + lane0; z < z1; z += 2 * G) {
+                int zb = z + G < z1 ? z + G : z;
+                int ca = A.col[z], cb = A.col[zb];
+                T va = A.val[z], vb = A.val[zb];
+                T xa = A.x[ca], xb = A.x[cb];
+                acc += va * xa + (z + G < z1 ? vb * xb : (T)0);
+            }
+        }
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) acc += __shfl_xor(acc, d, 64);
+        if (lane0 == 0 && valid && !heavy) {
+            A.xo[i] = acc;
+            double q = (double)acc;
+            if (DOT == 0) { s0 = q * q; s1 = q * (double)A.b[i]; }
+            else s0 = (double)q1[i] * q;
+        }
+    } else {
+        int w = ((int)blockIdx.x - A.nbs) * (BS / 64) + (int)(threadIdx.x >> 6);
+        int lane = threadIdx.x & 63;
+        if (w < A.nheavy) {
+            int i = A.heavy[w];
+            int z0 = A.rp[i], z1 = A.rp[i + 1];
+            T acc = (T)0;
+            for (int z = z0 + lane; z < z1; z += 256) {
+                T t[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    int zz = z + 64 * u < z1 ? z + 64 * u : z;
+                    T v = A.val[zz] * A.x[A.col[zz]];
+                    t[u] = z + 64 * u < z1 ? v : (T)0;
+                }
+                acc += (t[0] + t[1]) + (t[2] + t[3]);
+            }
+            for (int d = 1; d < 64; d <<= 1) acc += __shfl_xor(acc, d, 64);
+            if (lane == 0) {
+                A.xo[i] = acc;
+                double q = (double)acc;
+                if (DOT == 0) { s0 = q * q; s1 = q * (double)A.b[i]; }
+                else s0 = (double)q1[i] * q;
+            }
+        }
+    }
+    block_partials(s0, s1, part);
+}
+
+// ks = {q1.q1, a1, beta, a2} from nb partial pairs: step 0 from
+// (q1.q1, q1.b); 1 from q1.q2; 2 from (q2.q2, q2.r).  A zero denominator
+// gives a zero step.
+__global__ __launch_bounds__(1024) void k_kfin(int nb, const double *part, int step, double *ks) {
+    __shared__ double red[2][1024 / 64];
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) { s0 += part[b]; s1 += part[nb + b]; }
     for (int d = 32; d > 0; d >>= 1) {
         s0 += __shfl_xor(s0, d, 64);
         s1 += __shfl_xor(s1, d, 64);
@@ -915,7 +985,7 @@ __global__ __launch_bounds__(BS) void k_kfin(int nb, const double *part, int ste
     __syncthreads();
     if (threadIdx.x != 0) return;
     double t0 = 0.0, t1 = 0.0;
-    for (int q = 0; q < BS / 64; q++) { t0 += red[0][q]; t1 += red[1][q]; }
+    for (int q = 0; q < (int)(blockDim.x >> 6); q++) { t0 += red[0][q]; t1 += red[1][q]; }
     if (step == 0) {
         ks[0] = t0;
         ks[1] = t0 > 0.0 ? t1 / t0 : 0.0;
@@ -936,14 +1006,20 @@ __global__ void k_kres(int n, T *b, const T *q1, const double *ks, const T *l1, 
     x[i] = r / l1[i];
 }
 
-// p2 -= beta p1, q2 -= beta q1.
+// p2 -= beta p1, q2 -= beta q1, with partials of (q2.q2, q2.r) of the
+// updated q2 (grid-stride over KO_BLOCKS workgroups).
 template <class T>
-__global__ void k_korth(int n, const T *p1, T *p2, const T *q1, T *q2, const double *ks) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double beta = ks[2];
-    p2[i] = (T)((double)p2[i] - beta * (double)p1[i]);
-    q2[i] = (T)((double)q2[i] - beta * (double)q1[i]);
+__global__ __launch_bounds__(BS) void k_korth(int n, const T *p1, T *p2, const T *q1, T *q2,
+                                              const T *r, const double *ks, double *part) {
+    double beta = ks[2], s0 = 0.0, s1 = 0.0;
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) {
+        p2[i] = (T)((double)p2[i] - beta * (double)p1[i]);
+        T q = (T)((double)q2[i] - beta * (double)q1[i]);
+        q2[i] = q;
+        s0 += (double)q * (double)q;
+        s1 += (double)q * (double)r[i];
+    }
+    block_partials(s0, s1, part);
 }
 
 // Prolongation of the K-cycle correction: x_j += a1 p1[agg_j] + a2 p2[agg_j].
@@ -1009,14 +1085,6 @@ struct Cycle {
         R2P_LAUNCH();
         return 0;
     }
-    int dots(int n, const T *a0, const T *b0, const T *a1, const T *b1, int step, double *ks) {
-        int nb = std::max(1, std::min(KD_BLOCKS, r2p_blocks(n, BS)));
-        k_kdots<T><<<nb, BS, 0, s>>>(n, a0, b0, a1, b1, P->kpart.p);
-        R2P_LAUNCH();
-        k_kfin<<<1, BS, 0, s>>>(nb, P->kpart.p, step, ks);
-        R2P_LAUNCH();
-        return 0;
-    }
     // The coarse correction of level l, added to level l's iterate vx(l).
     int correct(int l) {
         AmgLevel &A = P->lv[l], &C = P->lv[l + 1];
@@ -1024,18 +1092,25 @@ struct Cycle {
         if (l < P->o.kcycle && c < nl - 1) {
             int n = C.n;
             T *p1 = kv(C), *p2 = p1 + n, *q1 = p2 + n, *q2 = q1 + n;
-            double *ks = P->kscal.p + 4 * c;
+            double *ks = P->kscal.p + 4 * c, *part = P->kpart.p;
+            int nbs = r2p_blocks(n, BS / G), nbk = nbs + r2p_blocks(C.nheavy, BS / 64);
+            int nbo = std::max(1, std::min(KO_BLOCKS, r2p_blocks(n, BS)));
             R2P_TRY(coarse(c, p1));
-            R2P_TRY(csr_launch<CSR_PRODUCT>(C, p1, q1));
-            R2P_TRY(dots(n, q1, q1, q1, vb(C), 0, ks));
+            k_kspmv<T, 0><<<nbk, BS, 0, s>>>(csr(C, p1, q1), nullptr, part);
+            R2P_LAUNCH();
+            k_kfin<<<1, 1024, 0, s>>>(nbk, part, 0, ks);
+            R2P_LAUNCH();
             k_kres<T><<<r2p_blocks(n, BS), BS, 0, s>>>(n, vb(C), q1, ks, l1s(C), vx(C));
             R2P_LAUNCH();
             R2P_TRY(coarse(c, p2));
-            R2P_TRY(csr_launch<CSR_PRODUCT>(C, p2, q2));
-            R2P_TRY(dots(n, q1, q2, nullptr, nullptr, 1, ks));
-            k_korth<T><<<r2p_blocks(n, BS), BS, 0, s>>>(n, p1, p2, q1, q2, ks);
+            k_kspmv<T, 1><<<nbk, BS, 0, s>>>(csr(C, p2, q2), q1, part);
             R2P_LAUNCH();
-            R2P_TRY(dots(n, q2, q2, q2, vb(C), 2, ks));
+            k_kfin<<<1, 1024, 0, s>>>(nbk, part, 1, ks);
+            R2P_LAUNCH();
+            k_korth<T><<<nbo, BS, 0, s>>>(n, p1, p2, q1, q2, vb(C), ks, part);
+            R2P_LAUNCH();
+            k_kfin<<<1, 1024, 0, s>>>(nbo, part, 2, ks);
+            R2P_LAUNCH();
             k_prolong_k<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, A.agg.p, p1, p2, ks, vx(A));
             R2P_LAUNCH();
         } else {

@@ -117,6 +117,13 @@ def _net_case(K, shape, seed):
 
 
 def test_network_forward_and_gradient_match_reference():
+    """The whole network against the reference with the device's bfloat16
+    rounding points (forward_bf16 / backward_bf16: activations and
+    back-propagated signals stored in bfloat16).  The two differ only where
+    an FP32 accumulation and the exact sum fall on opposite sides of a
+    bfloat16 rounding boundary: about 1e-4 of the elements, each by one
+    rounding (2^-8), so the relative 2-norm difference stays near 1e-4;
+    bound 1e-3 for the output, the loss and the parameter gradient."""
     from oracle import cnn
     r2p = _dev()
     K, shape = 1, (1, 4, 6, 8)
@@ -125,18 +132,20 @@ def test_network_forward_and_gradient_match_reference():
     net.set_params(theta.astype(np.float32))
     out = net.forward(f_t, shape)
     torch.cuda.synchronize()
-    ref_out, acts = cnn.forward(theta, f, 32, K)
+    ref_out, acts = cnn.forward_bf16(theta, f, 32, K)
     got = out.cpu().numpy().astype(np.float64)
     rel = np.linalg.norm(got - ref_out.reshape(-1)) / np.linalg.norm(ref_out)
-    assert rel < 0.02, rel
+    print(f"network output: relative difference {rel:.2e}")
+    assert rel < 1e-3, rel
     tgt_t = torch.from_numpy(tgt.reshape(-1).astype(np.float32)).cuda()
     loss = net.backward(f_t, tgt_t, shape)
     ref_loss = cnn.loss(ref_out, tgt)
-    assert abs(loss - ref_loss) <= 0.02 * ref_loss
+    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
     g = net.get_grads().astype(np.float64)
-    rg = cnn.backward(theta, acts, ref_out, tgt, 32, K)
+    rg = cnn.backward_bf16(theta, acts, ref_out, tgt, 32, K)
     rel_g = np.linalg.norm(g - rg) / np.linalg.norm(rg)
-    assert rel_g < 0.05, rel_g
+    print(f"network gradient: relative difference {rel_g:.2e}")
+    assert rel_g < 1e-3, rel_g
 
 
 def test_training_lowers_the_loss():

@@ -78,3 +78,25 @@ def test_bf16_rounding(v, bits):
     r = cnn.bf16_round(np.array([v]))
     u = np.float32(r[0]).view(np.uint32) >> 16
     assert int(u) == bits
+
+
+def test_bf16_network_reduces_to_the_fp64_network():
+    """forward_bf16 / backward_bf16 differ from the FP64 network only by the
+    bfloat16 roundings: with every value already representable (rounding is
+    then the identity on them) the two agree, and in general they differ by
+    about one rounding (2^-8 relative) per layer."""
+    from oracle import cnn
+    rng = np.random.default_rng(5)
+    K = 1
+    theta = cnn.bf16_round(cnn.init_params(rng, 8, K, out_scale=1.0))
+    f = cnn.bf16_round(rng.normal(size=(1, 3, 4, 5, cnn.NIN)))
+    tgt = rng.normal(size=(1, 3, 4, 5, cnn.NOUT))
+    o64, a64 = cnn.forward(theta, f, 8, K)
+    o16, a16 = cnn.forward_bf16(theta, f, 8, K)
+    for k in a16:
+        assert np.array_equal(cnn.bf16_round(a16[k]), a16[k])       # stored as bfloat16
+    rel = np.linalg.norm(o16 - o64) / np.linalg.norm(o64)
+    assert 0 < rel < 2 ** -6
+    g64 = cnn.backward(theta, a64, o64, tgt, 8, K)
+    g16 = cnn.backward_bf16(theta, a16, o16, tgt, 8, K)
+    assert np.linalg.norm(g16 - g64) / np.linalg.norm(g64) < 2 ** -5
