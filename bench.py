@@ -572,6 +572,8 @@ def main():
                     help="1: the 2M-cell model (default); 4: the 65.5M-cell channelised model, "
                          "FP64 against FP32 + learned start (its own JSON line)")
     ap.add_argument("--form", choices=["two-stage", "fpf"], default="two-stage")
+    ap.add_argument("--kcycle", type=int, default=2,
+                    help="AMG levels whose coarse correction is a K-cycle (0: V-cycle)")
     ap.add_argument("--tiles", type=lambda v: tuple(int(t) for t in v.split("x")), default=(16, 16),
                     help="RAS subdomain tiles PXxPY for --config 4 (default 16x16, one subdomain "
                          "per CU; at most 256 in all)")
@@ -592,7 +594,7 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="for hardware-counter runs: set up the first Newton system of the "
                          "workload, then run 5 RAS applies, 5 AMG cycles, 5 SpMVs and 5 copies "
-                         "of 512 MiB (the traffic calibration) and exit")
+                         "of 512 MiB (the traffic calibration), then 15 more AMG cycles, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): this build has no "
@@ -613,8 +615,8 @@ def main():
     x = model.initial_state()
     x_init = x.clone()
     form = r2p.CPR_FPF if args.form == "fpf" else r2p.CPR_TWO_STAGE
-    o64 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form))
-    o32 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, precision=r2p.FP32))
+    o64 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, kcycle=args.kcycle))
+    o32 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, precision=r2p.FP32, kcycle=args.kcycle))
     dt_max = float(w["dt"])
 
     if args.kernels_only:
@@ -632,6 +634,8 @@ def main():
             P.amg_vcycle(fp, xp)
             J.spmv(v, y)
             dst.copy_(src)
+        for _ in range(15):                 # more AMG cycles for per-level traces
+            P.amg_vcycle(fp, xp)
         torch.cuda.synchronize()
         rb, m_tot, nblk = ras_bytes(P, model, 8)
         print(json.dumps({"kernels_only": True, "ras_bytes_per_apply": rb,
