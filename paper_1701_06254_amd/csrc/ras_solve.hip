@@ -11,9 +11,11 @@
 //
 // One workgroup (8 wavefronts) processes one subdomain level by level, a
 // workgroup barrier between levels; a wavefront takes a slice of 32 rows of
-// a level, two lanes per row (each lane takes every other block of the row,
-// so the six couplings of a grid cell stay in registers), and the
-// wavefronts take the slices of the subdomain in turn.  Levels are a
+// a level, two lanes per row (each lane takes every other block of the row;
+// a lane holds two blocks in registers, which covers the L or U part of all
+// but a few rows: the rows of a slice with more than four blocks, well rows
+// and a few others, read the rest from memory), and the wavefronts take the
+// slices of the subdomain in turn.  Levels are a
 // latency chain, so nothing a step waits for is requested in that step:
 // the static data of a slice (columns, factor blocks, right-hand side) are
 // requested three and four steps ahead; the y values its rows need that
@@ -34,7 +36,7 @@ constexpr int WG = 1024;               // threads of a subdomain workgroup
 constexpr int NWAVE = WG / 64;
 constexpr int SWG = 512;               // sweep workgroup: 8 wavefronts, 256 VGPRs each
 constexpr int NCW = SWG / 64;          // sweep: wavefronts taking a subdomain's slices in turn
-constexpr int MAXK = 3;                // entries per lane held in registers (two lanes per row)
+constexpr int MAXK = 2;                // entries per lane held in registers (two lanes per row)
 constexpr int RAS_PAD = MAXK * RAS_SLICE;   // padding after the entry arrays: every task reads MAXK slot pairs
 constexpr int MAXLEV = 4096;           // levels per subdomain kept in LDS
 
@@ -701,7 +703,7 @@ struct Vec4 {
 };
 
 // The static data of one task (slice) held by the lane pair of each row:
-// lane h holds entries e = h, h + 2, h + 4 of the row (slot pairs k < MAXK),
+// lane h holds entries e = h, h + 2 of the row (slot pairs k < MAXK),
 // component h of the right-hand side and, backward, row h of the inverse
 // diagonal block; y values of entries finished before the prefetch was
 // issued arrive in yf.  st .. L are uniform.
@@ -777,9 +779,12 @@ __device__ __forceinline__ void prefetch_y(Task<T> &R, const int (&c)[MAXK], con
         int q = c[k];
         bool far = k < R.w && q >= 0 && q < mtot &&
                    (FWD ? q < bound && q < wl : q >= bound && q >= wl);
-        V2 v = *(const V2 *)&y[2 * (long)(far ? q : 0)];
-        R.yf[k][0] = v.x;
-        R.yf[k][1] = v.y;
+        // only the lanes with such an entry load (a few per task)
+        if (far) {
+            V2 v = *(const V2 *)&y[2 * (long)q];
+            R.yf[k][0] = v.x;
+            R.yf[k][1] = v.y;
+        }
     }
 }
 
@@ -855,7 +860,8 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
         t1 -= on[kk] ? d1 : (T)0;
     }
     if (cur.w > MAXK) {
-        // rows with more than 2 MAXK entries (well rows): the rest from memory
+        // rows with more than 2 MAXK entries (well rows and a few others): the
+        // rest from memory
         const int *cols = FWD ? A.lcol : A.ucol;
         const T *vals = FWD ? A.lval : A.uval;
         for (int kk = MAXK; kk < cur.w; kk++) {
