@@ -36,6 +36,7 @@ constexpr int WG = 1024;               // threads of a subdomain workgroup
 constexpr int NWAVE = WG / 64;
 constexpr int SWG = 512;               // sweep workgroup: 8 wavefronts, 256 VGPRs each
 constexpr int NCW = SWG / 64;          // sweep: wavefronts taking a subdomain's slices in turn
+constexpr int LK = 4;                  // sweep: slot pairs per round of a long (well) row
 constexpr int MAXK = 2;                // entries per lane held in registers (two lanes per row)
 constexpr int RAS_PAD = MAXK * RAS_SLICE;   // padding after the entry arrays: every task reads MAXK slot pairs
 constexpr int MAXLEV = 4096;           // levels per subdomain kept in LDS
@@ -864,19 +865,38 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
         // rest from memory
         const int *cols = FWD ? A.lcol : A.ucol;
         const T *vals = FWD ? A.lval : A.uval;
-        for (int kk = MAXK; kk < cur.w; kk++) {
-            long idx = (long)cur.b + (long)kk * RAS_SLICE + lane;
-            int q = cols[idx];
-            bool ok = q >= 0 && q < A.mtot;
-            int qs = ok ? q : 0;
-            bool inwin = FWD ? qs >= hi - win : qs < lo + win;
-            V2 gv = *(const V2 *)&A.y[2 * (long)qs];
-            V2 rv = *(const V2 *)&ring[2 * (qs & (R - 1))];
-            T a0 = inwin ? rv.x : gv.x, a1 = inwin ? rv.y : gv.y;
-            T e0 = vals[4 * idx] * a0 + vals[4 * idx + 1] * a1;
-            T e1 = vals[4 * idx + 2] * a0 + vals[4 * idx + 3] * a1;
-            t0 -= ok ? e0 : (T)0;
-            t1 -= ok ? e1 : (T)0;
+        // in rounds of LK slot pairs: the columns of a round, then its y values
+        // and blocks, are requested together (two dependent loads per round);
+        // pairs past the row's own re-read its last and are masked
+        typedef typename Vec4<T>::type V4;
+        for (int k0 = MAXK; k0 < cur.w; k0 += LK) {
+            long idx[LK];
+            int q[LK];
+#pragma unroll
+            for (int j = 0; j < LK; j++) {
+                idx[j] = (long)cur.b + (long)min(k0 + j, cur.w - 1) * RAS_SLICE + lane;
+                q[j] = cols[idx[j]];
+            }
+            V2 gv[LK], rv[LK];
+            V4 bv[LK];
+#pragma unroll
+            for (int j = 0; j < LK; j++) {
+                int qs = q[j] >= 0 && q[j] < A.mtot ? q[j] : 0;
+                gv[j] = *(const V2 *)&A.y[2 * (long)qs];
+                rv[j] = *(const V2 *)&ring[2 * (qs & (R - 1))];
+                bv[j] = *(const V4 *)&vals[4 * idx[j]];
+            }
+#pragma unroll
+            for (int j = 0; j < LK; j++) {
+                bool ok = k0 + j < cur.w && q[j] >= 0 && q[j] < A.mtot;
+                int qs = ok ? q[j] : 0;
+                bool inwin = FWD ? qs >= hi - win : qs < lo + win;
+                T a0 = inwin ? rv[j].x : gv[j].x, a1 = inwin ? rv[j].y : gv[j].y;
+                T e0 = bv[j].x * a0 + bv[j].y * a1;
+                T e1 = bv[j].z * a0 + bv[j].w * a1;
+                t0 -= ok ? e0 : (T)0;
+                t1 -= ok ? e1 : (T)0;
+            }
         }
         __builtin_amdgcn_s_waitcnt(0);
     }
