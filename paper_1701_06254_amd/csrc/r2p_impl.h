@@ -190,6 +190,7 @@ struct RasDyn {
     DBuf<int> sub_lbase;                  // ns: first segment of the subdomain
     DBuf<int> sub_nlev;                   // ns
     DBuf<int> counters;                   // scratch
+    DBuf<int> prog;                       // ns: sweep progress read by the prefetch helpers
     RasFactors<double> f64;
     RasFactors<float> f32;
 };

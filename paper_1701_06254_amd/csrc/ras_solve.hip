@@ -21,7 +21,11 @@
 // requested three and four steps ahead; the y values its rows need that
 // were finished two steps earlier are requested then; the rest were
 // finished in the last few levels and are read from an LDS ring that holds
-// the results of the most recent rows.  The gather of the right-hand side
+// the results of the most recent rows.  One CU streams a subdomain's factors
+// at the rate its outstanding L2 misses allow, so helper workgroups of the
+// same launch, placed on the subdomain's XCD, read the static data of the
+// slices some levels ahead of the sweep into that XCD's L2; the sweep then
+// finds them in L2 rather than in HBM.  The gather of the right-hand side
 // into local order and the restricted scatter of the result run as separate
 // full-device kernels.
 //
@@ -40,6 +44,7 @@ constexpr int LK = 4;                  // sweep: slot pairs per round of a long 
 constexpr int MAXK = 2;                // entries per lane held in registers (two lanes per row)
 constexpr int RAS_PAD = MAXK * RAS_SLICE;   // padding after the entry arrays: every task reads MAXK slot pairs
 constexpr int MAXLEV = 4096;           // levels per subdomain kept in LDS
+constexpr int PROG_STRIDE = 64;        // ints between two sweeps' progress counters
 
 // True when global row h precedes global row g in the local order.
 __device__ __forceinline__ bool before(int h, int g, int n, int order, const double *phi) {
@@ -640,8 +645,9 @@ __global__ void k_cast(long n, const double *a, T *b) {
 // contiguous along the tiles' rows; each row's pair lands at its position.
 template <class T>
 __global__ void k_ras_gather(int mtot, const int *glob_nat, const int *pos, const double *r,
-                             T *rl) {
+                             T *rl, int *prog, int ns) {
     int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < ns) prog[PROG_STRIDE * l] = 0;   // the sweeps' progress counters (read by the helpers)
     if (l >= mtot) return;
     long g = glob_nat[l], p = pos[l];
     const double2 v = ((const double2 *)r)[g];
@@ -677,8 +683,11 @@ struct SweepArgs {
     const int *lcol, *ucol;
     const T *lval, *uval, *dinv, *rl;
     T *y;
+    int *prog;                   // PROG_STRIDE ns: levels passed by each sweep (forward, then
+                                 // nlev + backward), one counter per 256 bytes
     int mtot;                    // local rows over all subdomains: the extent of y
     int ns;                      // subdomains (sweep workgroups)
+    int nhelp;                   // prefetch workgroups per subdomain (workgroups ns .. ns (1 + nhelp))
 };
 
 // LDS ring of the results of recently finished rows: position p sits in
@@ -812,6 +821,12 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
         __syncthreads();
         passed++;
     }
+    // every wavefront, every step: a store the helpers poll (unconditional, so
+    // the wait counts stay the same at every step).  Workgroup scope is enough:
+    // the store goes through to the XCD's L2, where the helpers' polls read,
+    // and nothing of the sweep's results depends on when they see it.
+    __hip_atomic_store(&A.prog[PROG_STRIDE * blockIdx.x], (FWD ? 0 : nlev) + passed,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     int lo = lp[cur.L], hi = lp[cur.L + 1];
     // entries of task k+2 finished by now and outside its ring window
     prefetch_y<T, FWD>(B[(U + 2) & 3], C[(U + 2) & 3], A.y, A.mtot, FWD ? lo : hi, lp, win);
@@ -956,6 +971,78 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *lp, 
         __syncthreads();
         passed++;
     }
+    __hip_atomic_store(&A.prog[PROG_STRIDE * blockIdx.x], (FWD ? 0 : nlev) + passed,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ------------------------------------------------------- prefetch helpers
+constexpr int PCH = 8;            // slices per helper chunk
+constexpr int PDS = 128;          // slices a chunk is read ahead of the sweep (about 0.8 MB)
+constexpr int PSPIN = 1 << 16;    // bound of a helper's wait for the sweep
+constexpr int MAX_HELP = 4;       // helper workgroups per subdomain
+
+// Read one dword of every 128-byte line of [p, p + bytes) (all addresses
+// inside the range); the values are summed only so that the loads stay.
+__device__ __forceinline__ unsigned touch(const void *p, long bytes) {
+    if (bytes < 4) return 0;
+    const char *c = (const char *)p;
+    const char *line0 = (const char *)((unsigned long)c & ~127ul);
+    long last = (long)(c + bytes - 4 - line0);          // offset of the range's last dword
+    long lines = last / 128 + 1;
+    unsigned acc = 0;
+    for (long i = threadIdx.x; i < lines; i += SWG) {
+        const char *a = line0 + i * 128;
+        a = a < c ? c : a;
+        a = a > c + bytes - 4 ? c + bytes - 4 : a;
+        acc += *(const unsigned *)((unsigned long)a & ~3ul);
+    }
+    return acc;
+}
+
+// Helper j of subdomain s, one direction: chunks j, j + H, ... of PCH
+// slices in the sweep's order; each waits (bounded) until the sweep has
+// finished all but PDS of the slices before it, then reads the chunk's
+// metadata, columns, factor blocks and right-hand side (backward: the forward
+// result and the inverse diagonal blocks).
+template <class T, bool FWD>
+__device__ unsigned prefetch_dir(const SweepArgs<T> &A, int s, int j, int H, int sa, int sb,
+                                 int nlev, int base) {
+    const int4 *meta = FWD ? A.mL : A.mU;
+    const int *cols = FWD ? A.lcol : A.ucol;
+    const T *vals = FWD ? A.lval : A.uval;
+    int nsl = sb - sa;
+    unsigned acc = 0;
+    for (int c = j; c * PCH < nsl; c += H) {
+        int i0 = c * PCH, i1 = min(i0 + PCH, nsl);
+        int f = FWD ? sa + i0 : sb - i1;           // lowest and highest slice of the chunk
+        int l = FWD ? sa + i1 - 1 : sb - 1 - i0;
+        int4 mf = meta[f], ml = meta[l];
+        // one lane polls (the counter's line is written at every step of the
+        // sweep), the workgroup waits for it
+        if (threadIdx.x == 0) {
+            for (int spin = 0; spin < PSPIN; spin++) {
+                int pr = __hip_atomic_load(&A.prog[PROG_STRIDE * s], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                // slices the sweep has finished in this direction
+                int done;
+                if (FWD)
+                    done = pr >= nlev ? nsl : A.soff[base + max(pr, 0)] - sa;
+                else
+                    done = pr < nlev ? -1 : sb - A.soff[base + nlev - min(pr - nlev, nlev)];
+                if (i0 - done <= PDS) break;
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        __syncthreads();
+        long e0 = mf.z, e1 = (long)ml.z + (long)(ml.y >> 8) * RAS_SLICE;
+        long p0 = mf.x, p1 = (long)ml.x + (ml.y & 255);
+        acc += touch(meta + f, 16L * (l - f + 1));
+        acc += touch(cols + e0, 4L * (e1 - e0));
+        acc += touch(vals + 4 * e0, 4L * (long)sizeof(T) * (e1 - e0));
+        acc += touch((FWD ? A.rl : (const T *)A.y) + 2 * p0, 2L * (long)sizeof(T) * (p1 - p0));
+        if (!FWD) acc += touch(A.dinv + 4 * p0, 4L * (long)sizeof(T) * (p1 - p0));
+    }
+    return acc;
 }
 
 // Forward then backward substitution of one subdomain per workgroup on the
@@ -966,6 +1053,17 @@ __global__ __launch_bounds__(SWG) void k_ras_sweep(SweepArgs<T> A) {
     __shared__ int lp[MAXLEV + 1];
     __shared__ int maxw;
     __shared__ __attribute__((aligned(16))) T ring[2 * R];
+    if ((int)blockIdx.x >= A.ns) {
+        // a helper: subdomain (b - ns) mod ns, on the same XCD as its sweep
+        // (workgroup b goes to XCD b mod 8 and ns is a multiple of 8)
+        int hb = blockIdx.x - A.ns, hs = hb % A.ns;
+        int hn = A.nlev[hs], hbase = A.lbase[hs];
+        int hsa = A.soff[hbase], hsb = A.soff[hbase + hn];
+        unsigned acc = prefetch_dir<T, true>(A, hs, hb / A.ns, A.nhelp, hsa, hsb, hn, hbase);
+        acc += prefetch_dir<T, false>(A, hs, hb / A.ns, A.nhelp, hsa, hsb, hn, hbase);
+        if (A.nhelp < 0) A.prog[0] = (int)acc;     // never taken; keeps the reads
+        return;
+    }
     int s = blockIdx.x;
     int nlev = A.nlev[s], base = A.lbase[s];
     if (threadIdx.x == 0) maxw = 0;
@@ -1018,6 +1116,7 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
     R2P_TRY(D.sl_of.ensure(mtot));
     R2P_TRY(D.dsrc_pos.ensure(mtot));
     R2P_TRY(D.counters.ensure(64 + 2 * ns));
+    R2P_TRY(D.prog.ensure(PROG_STRIDE * ns));
     R2P_TRY(P->pin.ensure(1 << 16));
     int nb = r2p_blocks(mtot, BS);
     // 1. levels of the dependency graph
@@ -1190,7 +1289,8 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     RasDyn &D = P->rd;
     int mtot = P->rs.mtot;
     int nb = r2p_blocks(mtot, BS);
-    k_ras_gather<T><<<nb, BS, 0, s>>>(mtot, P->rs.glob_nat.p, D.pos.p, r, rl);
+    int ns = P->rs.ns;
+    k_ras_gather<T><<<nb, BS, 0, s>>>(mtot, P->rs.glob_nat.p, D.pos.p, r, rl, D.prog.p, ns);
     R2P_LAUNCH();
     SweepArgs<T> A;
     A.lbase = D.sub_lbase.p; A.nlev = D.sub_nlev.p; A.soff = D.soff.p; A.lptr = D.lptr_dev.p;
@@ -1198,9 +1298,11 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     A.lcol = D.lcol.p; A.ucol = D.ucol.p;
     A.lval = F.lval.p; A.uval = F.uval.p; A.dinv = F.dinv.p; A.rl = rl; A.y = y;
     A.mtot = mtot;
-    int ns = P->rs.ns;
     A.ns = ns;
-    k_ras_sweep<T><<<ns, SWG, 0, s>>>(A);
+    A.prog = D.prog.p;
+    // helpers only where they fit beside the sweeps and share their XCDs
+    A.nhelp = ns % 8 == 0 ? std::max(0, std::min(MAX_HELP, 256 / ns - 1)) : 0;
+    k_ras_sweep<T><<<ns * (1 + A.nhelp), SWG, 0, s>>>(A);
     R2P_LAUNCH();
     k_ras_scatter<T><<<nb, BS, 0, s>>>(mtot, P->J->m->ph.n, D.glob.p, D.owned.p, y, xp,
                                        accumulate, out);
