@@ -19,8 +19,9 @@ under the library's rules (the scaled-residual rule, and the try rule);
 Newton and linear iterations and wall time are reported per form.
 
 Usage: python -m paper_1701_06254_amd.learned_study [--train-seeds 8]
-[--steps 12] [--eval-seeds 3] [--iters 3000] [--out FILE.json]
-[--weights FILE.npy].  Only the C ABI does arithmetic; this script moves
+[--steps 12] [--crops 52] [--eval-seeds 10] [--iters 6000] [--out FILE.json]
+[--weights FILE.npy].  The defaults give about 5,000 training crops (96
+increments of 8 runs, 52 crops each) and evaluate on seeds 9000-9009.  Only the C ABI does arithmetic; this script moves
 tensors and records results.
 """
 from __future__ import annotations
@@ -152,10 +153,10 @@ def main(argv=None):
     from . import r2p, warmstart
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-seeds", type=int, default=8)
-    ap.add_argument("--eval-seeds", type=int, default=3)
+    ap.add_argument("--eval-seeds", type=int, default=10)
     ap.add_argument("--steps", type=int, default=12)
-    ap.add_argument("--crops", type=int, default=4)
-    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--crops", type=int, default=52)
+    ap.add_argument("--iters", type=int, default=6000)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default=None)
