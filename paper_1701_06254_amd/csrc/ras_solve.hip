@@ -38,8 +38,14 @@
 constexpr int BS = 256;
 constexpr int WG = 1024;               // threads of a subdomain workgroup
 constexpr int NWAVE = WG / 64;
-constexpr int SWG = 512;               // sweep workgroup: 8 wavefronts, 256 VGPRs each
-constexpr int NCW = SWG / 64;          // sweep: wavefronts taking a subdomain's slices in turn
+// Sweep workgroup: 8 wavefronts of up to 256 VGPRs (FP64), 12 of up to 168
+// (FP32, whose buffers fit in that); the wavefronts take a subdomain's slices
+// in turn.
+template <class T>
+struct Sweep {
+    static constexpr int wg = sizeof(T) == 4 ? 768 : 512;
+    static constexpr int ncw = wg / 64;
+};
 constexpr int LK = 4;                  // sweep: slot pairs per round of a long (well) row
 constexpr int MAXK = 2;                // entries per lane held in registers (two lanes per row)
 constexpr int RAS_PAD = MAXK * RAS_SLICE;   // padding after the entry arrays: every task reads MAXK slot pairs
@@ -728,7 +734,7 @@ struct Task {
 // Slice of task j of a wavefront: the wavefronts take the slices of the
 // subdomain in turn (forward from the first, backward from the last).  Past
 // the wavefront's last task the last one is repeated (prefetches only).
-template <bool FWD>
+template <bool FWD, int NCW>
 __device__ __forceinline__ int task_slice(int sa, int sb, int wave, int j, int nt) {
     int jj = j < nt ? j : nt - 1;
     return FWD ? sa + wave + NCW * jj : sb - 1 - wave - NCW * jj;
@@ -861,7 +867,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
     }
     __builtin_amdgcn_sched_barrier(0);
     // metadata of task k+6, columns of task k+4, values of task k+3
-    M[(U + 2) & 3] = meta[task_slice<FWD>(sa, sb, wave, k + 6, nt)];
+    M[(U + 2) & 3] = meta[task_slice<FWD, Sweep<T>::ncw>(sa, sb, wave, k + 6, nt)];
     load_cols<T, FWD>(C[U], A, M[U], lane);
     load_task<T, FWD>(B[(U + 3) & 3], A, M[(U + 3) & 3], lane);
     __builtin_amdgcn_sched_barrier(0);
@@ -935,6 +941,7 @@ template <class T, bool FWD>
 __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *lp, T *ring, int win,
                                           int sa, int sb, int nlev, int wave, int lane) {
     int nsl = sb - sa;
+    constexpr int NCW = Sweep<T>::ncw;
     int nt = nsl > wave ? (nsl - wave + NCW - 1) / NCW : 0;
     int passed = 0;
     if (nt > 0) {
@@ -943,13 +950,13 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *lp, 
         int C[4][MAXK];
         int4 M[4];
 #pragma unroll
-        for (int j = 0; j < 4; j++) M[j] = meta[task_slice<FWD>(sa, sb, wave, j, nt)];
+        for (int j = 0; j < 4; j++) M[j] = meta[task_slice<FWD, Sweep<T>::ncw>(sa, sb, wave, j, nt)];
 #pragma unroll
         for (int j = 0; j < 4; j++) load_cols<T, FWD>(C[j], A, M[j], lane);
 #pragma unroll
         for (int j = 0; j < 3; j++) load_task<T, FWD>(B[j], A, M[j], lane);
-        M[0] = meta[task_slice<FWD>(sa, sb, wave, 4, nt)];
-        M[1] = meta[task_slice<FWD>(sa, sb, wave, 5, nt)];
+        M[0] = meta[task_slice<FWD, Sweep<T>::ncw>(sa, sb, wave, 4, nt)];
+        M[1] = meta[task_slice<FWD, Sweep<T>::ncw>(sa, sb, wave, 5, nt)];
         // nothing is finished before the first two tasks
         B[0].pf = B[1].pf = FWD ? lp[0] : lp[nlev];
         // enter the loop with nothing in flight, so that the wait counts the
@@ -990,7 +997,7 @@ __device__ __forceinline__ unsigned touch(const void *p, long bytes) {
     long last = (long)(c + bytes - 4 - line0);          // offset of the range's last dword
     long lines = last / 128 + 1;
     unsigned acc = 0;
-    for (long i = threadIdx.x; i < lines; i += SWG) {
+    for (long i = threadIdx.x; i < lines; i += blockDim.x) {
         const char *a = line0 + i * 128;
         a = a < c ? c : a;
         a = a > c + bytes - 4 ? c + bytes - 4 : a;
@@ -1048,7 +1055,7 @@ __device__ unsigned prefetch_dir(const SweepArgs<T> &A, int s, int j, int H, int
 // Forward then backward substitution of one subdomain per workgroup on the
 // gathered right-hand side; the result overwrites y in local order.
 template <class T>
-__global__ __launch_bounds__(SWG) void k_ras_sweep(SweepArgs<T> A) {
+__global__ __launch_bounds__(Sweep<T>::wg) void k_ras_sweep(SweepArgs<T> A) {
     constexpr int R = RingSize<T>::rows;
     __shared__ int lp[MAXLEV + 1];
     __shared__ int maxw;
@@ -1067,10 +1074,10 @@ __global__ __launch_bounds__(SWG) void k_ras_sweep(SweepArgs<T> A) {
     int s = blockIdx.x;
     int nlev = A.nlev[s], base = A.lbase[s];
     if (threadIdx.x == 0) maxw = 0;
-    for (int i = threadIdx.x; i < 2 * R; i += SWG) ring[i] = (T)0;
+    for (int i = threadIdx.x; i < 2 * R; i += Sweep<T>::wg) ring[i] = (T)0;
     __syncthreads();
     int mw = 0;
-    for (int L = threadIdx.x; L <= nlev; L += SWG) {
+    for (int L = threadIdx.x; L <= nlev; L += Sweep<T>::wg) {
         lp[L] = A.lptr[base + L];
         if (L < nlev) mw = max(mw, A.lptr[base + L + 1] - A.lptr[base + L]);
     }
@@ -1302,7 +1309,7 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     A.prog = D.prog.p;
     // helpers only where they fit beside the sweeps and share their XCDs
     A.nhelp = ns % 8 == 0 ? std::max(0, std::min(MAX_HELP, 256 / ns - 1)) : 0;
-    k_ras_sweep<T><<<ns * (1 + A.nhelp), SWG, 0, s>>>(A);
+    k_ras_sweep<T><<<ns * (1 + A.nhelp), Sweep<T>::wg, 0, s>>>(A);
     R2P_LAUNCH();
     k_ras_scatter<T><<<nb, BS, 0, s>>>(mtot, P->J->m->ph.n, D.glob.p, D.owned.p, y, xp,
                                        accumulate, out);
