@@ -663,13 +663,17 @@ __global__ void k_ras_gather(int mtot, const int *glob_nat, const int *pos, cons
 
 // Restricted scatter: owned rows only; optional Pi_p addend on the pressure
 // and accumulation into out (out = (out + Pi_p xp) + z, Algorithm 2's order).
+// One thread per local row in natural order, like the gather, so that the
+// writes to out are contiguous along the tiles' rows; each row reads its pair
+// at its position.
 template <class T>
-__global__ void k_ras_scatter(int mtot, int n, const int *glob, const unsigned char *owned,
-                              const T *y, const double *xp, int accumulate, double *out) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= mtot || !owned[p]) return;
-    long g = glob[p];
-    double o0 = (double)y[2 * (long)p], o1 = (double)y[2 * (long)p + 1];
+__global__ void k_ras_scatter(int mtot, int n, const int *glob_nat, const unsigned char *owned_nat,
+                              const int *pos, const T *y, const double *xp, int accumulate,
+                              double *out) {
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= mtot || !owned_nat[l]) return;
+    long g = glob_nat[l], p = pos[l];
+    double o0 = (double)y[2 * p], o1 = (double)y[2 * p + 1];
     if (accumulate) {
         double v0 = out[2 * g];
         if (xp && g < n) v0 += xp[g];
@@ -1311,7 +1315,8 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     A.nhelp = ns % 8 == 0 ? std::max(0, std::min(MAX_HELP, 256 / ns - 1)) : 0;
     k_ras_sweep<T><<<ns * (1 + A.nhelp), Sweep<T>::wg, 0, s>>>(A);
     R2P_LAUNCH();
-    k_ras_scatter<T><<<nb, BS, 0, s>>>(mtot, P->J->m->ph.n, D.glob.p, D.owned.p, y, xp,
+    k_ras_scatter<T><<<nb, BS, 0, s>>>(mtot, P->J->m->ph.n, P->rs.glob_nat.p, P->rs.owned_nat.p,
+                                       D.pos.p, y, xp,
                                        accumulate, out);
     R2P_LAUNCH();
     return 0;
