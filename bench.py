@@ -572,7 +572,9 @@ def main():
                     help="1: the 2M-cell model (default); 4: the 65.5M-cell channelised model, "
                          "FP64 against FP32 + learned start (its own JSON line)")
     ap.add_argument("--form", choices=["two-stage", "fpf"], default="two-stage")
-    ap.add_argument("--kcycle", type=int, default=2,
+    ap.add_argument("--amg-cycles", type=int, default=None,
+                    help="AMG cycles per pressure stage (default: the library's)")
+    ap.add_argument("--kcycle", type=int, default=1,
                     help="AMG levels whose coarse correction is a K-cycle (0: V-cycle)")
     ap.add_argument("--tiles", type=lambda v: tuple(int(t) for t in v.split("x")), default=(16, 16),
                     help="RAS subdomain tiles PXxPY for --config 4 (default 16x16, one subdomain "
@@ -615,8 +617,9 @@ def main():
     x = model.initial_state()
     x_init = x.clone()
     form = r2p.CPR_FPF if args.form == "fpf" else r2p.CPR_TWO_STAGE
-    o64 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, kcycle=args.kcycle))
-    o32 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, precision=r2p.FP32, kcycle=args.kcycle))
+    ac = {} if args.amg_cycles is None else {"amg_cycles": args.amg_cycles}
+    o64 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, kcycle=args.kcycle, **ac))
+    o32 = r2p.newton_opts(cpr=r2p.cpr_opts(form=form, precision=r2p.FP32, kcycle=args.kcycle, **ac))
     dt_max = float(w["dt"])
 
     if args.kernels_only:
@@ -661,7 +664,8 @@ def main():
         "config": {"workload": f"{w['name']}: {w['grid']['n']} cells, {len(w['wells'])} wells, "
                                f"adaptive dt from {DT_INIT} d (max {dt_max} d); CPR {args.form}, "
                                "QI + local potential order, RAS 4x4 overlap 1 BILU(0), "
-                               "aggregation AMG with K-cycle on the two finest levels, "
+                               "aggregation AMG, two cycles per pressure stage, K-cycle "
+                               "on the first coarse level, "
                                "FGMRES(30) rtol 1e-8",
                    "cells": w["grid"]["n"], "form": args.form},
         "dt_days": accepted,
@@ -806,7 +810,7 @@ def main():
     # ---- Krylov methods and the method variants on the last Newton system
     def krylov_leg():
         res = {}
-        for name, method, kc in (("fgmres", r2p.KRYLOV_FGMRES, 2),
+        for name, method, kc in (("fgmres", r2p.KRYLOV_FGMRES, 1),
                                  ("fgmres_vcycle", r2p.KRYLOV_FGMRES, 0),
                                  ("bicgstab_vcycle", r2p.KRYLOV_BICGSTAB, 0)):
             J = r2p.Jacobian(model)

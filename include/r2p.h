@@ -104,7 +104,9 @@ typedef struct {
                           generalised-conjugate-residual steps, each preconditioned by a
                           cycle one level down (K-cycle); 0 gives the V-cycle.  A K-cycle
                           makes the preconditioner vary with its input: use it with the
-                          flexible GMRES, not with BiCGSTAB (2) */
+                          flexible GMRES, not with BiCGSTAB (1) */
+    int amg_cycles;    /* AMG: cycles per pressure stage (1..8), each on the residual of the
+                          last: x_p = C(r_p), then x_p = x_p + C(r_p - A_pp x_p) (2) */
 } r2p_cpr_opts;
 
 enum { R2P_KRYLOV_FGMRES = 0, R2P_KRYLOV_BICGSTAB = 1 };

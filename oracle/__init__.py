@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "_build", "liboracle.so")
 DEC_NONE, DEC_QI, DEC_ABF = 0, 1, 2
 ORD_NATURAL, ORD_POTENTIAL = 0, 1
 CPR_TWO_STAGE, CPR_FPF = 0, 1
+AMG_CYCLES = 2      # AMG cycles per pressure stage (the default of both sides)
 
 _lib = None
 
@@ -63,14 +64,14 @@ class CprOpts(C.Structure):
                 ("px", C.c_int), ("py", C.c_int), ("overlap", C.c_int),
                 ("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int),
                 ("match_rounds", C.c_int), ("agg_passes", C.c_int), ("kcycle", C.c_int),
-                ("exact_stages", C.c_int)]
+                ("amg_cycles", C.c_int), ("exact_stages", C.c_int)]
 
 
 def cpr_opts(decouple=DEC_QI, order=ORD_POTENTIAL, form=CPR_TWO_STAGE, px=4, py=4, overlap=1,
-             theta=0.25, max_coarse=500, max_levels=20, match_rounds=4, agg_passes=2, kcycle=2,
-             exact_stages=0):
+             theta=0.25, max_coarse=500, max_levels=20, match_rounds=4, agg_passes=2, kcycle=1,
+             amg_cycles=AMG_CYCLES, exact_stages=0):
     return CprOpts(decouple, order, form, px, py, overlap, theta, max_coarse, max_levels,
-                   match_rounds, agg_passes, kcycle, exact_stages)
+                   match_rounds, agg_passes, kcycle, amg_cycles, exact_stages)
 
 
 def lib():

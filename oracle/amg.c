@@ -370,6 +370,25 @@ void om_amg_vcycle(const om_amg *H, const double *b, double *x)
     cycle(H, 0, b, x);
 }
 
+/* ncyc cycles on A_0 x = b from x = 0, each on the residual of the last:
+ * x = C(b); then x = x + C(b - A_0 x), ncyc - 1 times (an AMG-preconditioned
+ * Richardson iteration on the pressure system; reading B6h). */
+void om_amg_cycles(const om_amg *H, const double *b, double *x, int ncyc)
+{
+    cycle(H, 0, b, x);
+    int n = H->A[0].n;
+    if (ncyc < 2 || n < 1) return;
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *c = (double *)malloc(sizeof(double) * n);
+    for (int k = 1; k < ncyc; k++) {
+        csr_resid(&H->A[0], b, x, r);
+        cycle(H, 0, r, c);
+        for (int i = 0; i < n; i++) x[i] = x[i] + c[i];
+    }
+    free(r);
+    free(c);
+}
+
 void om_amg_free(om_amg *H)
 {
     for (int k = 0; k < H->nlev; k++) {

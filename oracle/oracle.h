@@ -101,6 +101,7 @@ typedef struct {
     double theta;         /* AMG strength threshold */
     int max_coarse, max_levels, match_rounds, agg_passes;
     int kcycle;           /* AMG levels whose coarse correction is a K-cycle */
+    int amg_cycles;       /* AMG cycles per pressure stage, each on the last residual */
     int exact_stages;     /* 1: RAS and V-cycle replaced by dense solves (pin of Alg 2) */
 } om_cpr_opts;
 
@@ -165,6 +166,7 @@ void om_bilu0_solve(const om_bsr *LU, const double *dinv, const int *diag, doubl
 int  om_amg_setup(om_amg *H, const om_csr *A0, double theta, int max_coarse, int max_levels,
                   int rounds, int passes, int kcycle);
 void om_amg_vcycle(const om_amg *H, const double *b, double *x);
+void om_amg_cycles(const om_amg *H, const double *b, double *x, int ncyc);
 void om_amg_free(om_amg *H);
 void om_extract_pressure(const om_bsr *A, int ncell, om_csr *App);
 void om_strength_match(const om_csr *A, double theta, int rounds, int *match);

@@ -69,7 +69,7 @@ static void stage_ras(const om_cpr *P, const double *r, double *y)
     }
 }
 
-/* x_p = M(A_pp)^-1 (Pi_r r) */
+/* x_p = M(A_pp)^-1 (Pi_r r), M(A_pp)^-1 being amg_cycles AMG cycles */
 static void stage_amg(const om_cpr *P, const double *r, double *xp)
 {
     int n = P->ncell;
@@ -79,7 +79,7 @@ static void stage_amg(const om_cpr *P, const double *r, double *xp)
         memcpy(xp, rp, sizeof(double) * n);
         om_dense_lu_solve(n, P->dense_App, P->piv_App, xp);
     } else {
-        om_amg_vcycle(&P->amg, rp, xp);
+        om_amg_cycles(&P->amg, rp, xp, P->o.amg_cycles);
     }
     free(rp);
 }

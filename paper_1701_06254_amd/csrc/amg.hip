@@ -1174,6 +1174,57 @@ int r2p_amg_cycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStrea
     return c.run(f, fstride, xp);
 }
 
+// r = f - A_pp xp on level 0 (the 7-slot stencil, summed as in k_up0), FP64.
+template <class T>
+__global__ void k_res0(Level0<T> A, const double *xp, double *r) {
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int order[7] = {5, 3, 1, 0, 2, 4, 6};
+    double s = A.f[(long)A.fstride * i];
+#pragma unroll
+    for (int oi = 0; oi < 7; oi++) {
+        int sl = order[oi];
+        int j = i + slot_offset(sl, A.nx, A.nxy);
+        j = j < 0 ? 0 : (j >= A.n ? A.n - 1 : j);
+        s -= (double)ld_stream(&A.v7[(long)sl * A.n + i]) * xp[j];
+    }
+    r[i] = s;
+}
+
+__global__ void k_add(int n, const double *c, double *x) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = x[i] + c[i];
+}
+
+// The pressure stage: amg_cycles cycles on A_pp xp = f_p from xp = 0, each
+// on the residual of the last (xp = C(f_p), then xp = xp + C(f_p - A_pp xp)).
+template <class T>
+static int amg_apply_t(r2p_cpr *P, const double *f, int fstride, double *xp, hipStream_t s) {
+    R2P_TRY(r2p_amg_cycle(P, f, fstride, xp, s));
+    if (P->o.amg_cycles < 2 || P->nlev < 2) return 0;
+    AmgLevel &A = P->lv[0];
+    const Phys &ph = P->J->m->ph;
+    Level0<T> Z;
+    Z.n = A.n; Z.nx = ph.nx; Z.nxy = ph.nx * ph.ny;
+    if constexpr (sizeof(T) == 4) Z.v7 = A.v7f.p; else Z.v7 = (const T *)A.v7.p;
+    Z.l1 = nullptr;
+    Z.f = f;
+    Z.fstride = fstride;
+    for (int k = 1; k < P->o.amg_cycles; k++) {
+        k_res0<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(Z, xp, P->t_ares.p);
+        R2P_LAUNCH();
+        R2P_TRY(r2p_amg_cycle(P, P->t_ares.p, 1, P->t_acor.p, s));
+        k_add<<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, P->t_acor.p, xp);
+        R2P_LAUNCH();
+    }
+    return 0;
+}
+
+int r2p_amg_apply(r2p_cpr *P, const double *f, int fstride, double *xp, hipStream_t s) {
+    if (P->o.precision == R2P_FP32) return amg_apply_t<float>(P, f, fstride, xp, s);
+    return amg_apply_t<double>(P, f, fstride, xp, s);
+}
+
 extern "C" int r2p_amg_info(r2p_cpr *P, int level, int *nlev, int *n, int *nnz) {
     if (!P || !P->ready) { r2p_set_error("CPR not set up"); return R2P_ESTATE; }
     if (nlev) *nlev = P->nlev;

@@ -252,6 +252,7 @@ struct r2p_cpr {
     DBuf<int> piv;
     DBuf<double> kscal;      // K-cycle scalars {q1.q1, a1, beta, a2} per level
     DBuf<double> kpart;      // K-cycle dot-product partial sums
+    DBuf<double> t_ares, t_acor;   // pressure stage: residual and correction of the later cycles
     DBuf<int> status;        // device status flags
     // level-0 structure cache, and the model the cached structures belong to
     int app_n = -1;
@@ -360,6 +361,7 @@ int r2p_amg_setup(r2p_cpr *P, hipStream_t s);
 int r2p_ras_solve(r2p_cpr *P, const double *r, double *out, const double *xp, int accumulate,
                   hipStream_t s);
 int r2p_amg_cycle(r2p_cpr *P, const double *f, int fstride, double *xp, hipStream_t s);
+int r2p_amg_apply(r2p_cpr *P, const double *f, int fstride, double *xp, hipStream_t s);
 int r2p_pcol_residual(r2p_jacobian *J, const double *f, const double *xp, double *r,
                       hipStream_t s);
 int r2p_decouple_jacobian(r2p_jacobian *J, int kind, hipStream_t s);

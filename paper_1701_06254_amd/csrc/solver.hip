@@ -249,12 +249,12 @@ int r2p_cpr_apply_impl(r2p_cpr *P, const double *f, double *z, hipStream_t s) {
         // r = f - A x; x += R^-1 r
         R2P_TRY(r2p_ras_solve(P, f, z, nullptr, 0, s));
         R2P_TRY(r2p_spmv_impl(J, z, P->t_r.p, f, s));
-        R2P_TRY(r2p_amg_cycle(P, P->t_r.p, 2, P->t_xp.p, s));
+        R2P_TRY(r2p_amg_apply(P, P->t_r.p, 2, P->t_xp.p, s));
         R2P_TRY(r2p_pcol_residual(J, P->t_r.p, P->t_xp.p, P->t_y.p, s));
         R2P_TRY(r2p_ras_solve(P, P->t_y.p, z, P->t_xp.p, 1, s));
     } else {
         // x = Pi_p M^-1 Pi_r f; r = f - A x; x += R^-1 r
-        R2P_TRY(r2p_amg_cycle(P, f, 2, P->t_xp.p, s));
+        R2P_TRY(r2p_amg_apply(P, f, 2, P->t_xp.p, s));
         R2P_TRY(r2p_pcol_residual(J, f, P->t_xp.p, P->t_r.p, s));
         R2P_TRY(r2p_ras_solve(P, P->t_r.p, z, P->t_xp.p, 0, s));
     }
@@ -341,7 +341,8 @@ static int check_opts(const r2p_cpr_opts *o) {
         o->form > 1 || o->px < 1 || o->py < 1 || o->px * o->py > 256 || o->overlap < 0 ||
         o->overlap > 8 || !(o->theta >= 0) || o->max_coarse < 1 || o->max_coarse > 2048 ||
         o->max_levels < 1 || o->match_rounds < 1 || o->agg_passes < 1 || o->agg_passes > 4 ||
-        o->precision < 0 || o->precision > 1 || o->kcycle < 0 || o->kcycle > 23) {
+        o->precision < 0 || o->precision > 1 || o->kcycle < 0 || o->kcycle > 23 ||
+        o->amg_cycles < 1 || o->amg_cycles > 8) {
         r2p_set_error("invalid CPR options");
         return R2P_EINVAL;
     }
@@ -368,6 +369,10 @@ extern "C" int r2p_setup_cpr(r2p_jacobian *J, const r2p_cpr_opts *o, r2p_cpr *P,
     R2P_TRY(P->t_r.ensure(N));
     R2P_TRY(P->t_y.ensure(N));
     R2P_TRY(P->t_xp.ensure(ph.n));
+    if (o->amg_cycles > 1) {
+        R2P_TRY(P->t_ares.ensure(ph.n));
+        R2P_TRY(P->t_acor.ensure(ph.n));
+    }
     P->ms_dec = P->ms_order = P->ms_ras = P->ms_amg = 0.0;
     double t0 = r2p_now_ms();
     R2P_TRY(r2p_decouple_jacobian(J, o->decouple, s));
@@ -631,7 +636,8 @@ extern "C" void r2p_default_newton_opts(r2p_newton_opts *o) {
     o->cpr.match_rounds = 4;
     o->cpr.agg_passes = 2;
     o->cpr.precision = R2P_FP64;
-    o->cpr.kcycle = 2;
+    o->cpr.kcycle = 1;
+    o->cpr.amg_cycles = 2;
     o->lin.restart = 30;
     o->lin.maxit = 300;
     o->lin.rtol = 1e-8;

@@ -46,7 +46,7 @@ class CprOpts(C.Structure):
                 ("px", C.c_int), ("py", C.c_int), ("overlap", C.c_int),
                 ("theta", C.c_double), ("max_coarse", C.c_int), ("max_levels", C.c_int),
                 ("match_rounds", C.c_int), ("agg_passes", C.c_int), ("precision", C.c_int),
-                ("kcycle", C.c_int)]
+                ("kcycle", C.c_int), ("amg_cycles", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -77,9 +77,9 @@ class NewtonInfo(C.Structure):
 
 def cpr_opts(decouple=DEC_QI, order=ORDER_POTENTIAL, form=CPR_TWO_STAGE, px=4, py=4, overlap=1,
              theta=0.25, max_coarse=500, max_levels=20, match_rounds=4, agg_passes=2,
-             precision=FP64, kcycle=2):
+             precision=FP64, kcycle=1, amg_cycles=2):
     return CprOpts(decouple, order, form, px, py, overlap, theta, max_coarse, max_levels,
-                   match_rounds, agg_passes, precision, kcycle)
+                   match_rounds, agg_passes, precision, kcycle, amg_cycles)
 
 
 KRYLOV_FGMRES, KRYLOV_BICGSTAB = 0, 1

@@ -226,11 +226,12 @@ def test_ras_factors_match(dev, orc, order):
     _assert_vec_close(yg, yo, 1e-10, 2 * mo.nw)
 
 
-@pytest.mark.parametrize("form", [0, 1])
-def test_cpr_apply_matches(dev, orc, form):
+@pytest.mark.parametrize("form,ncyc", [(0, 1), (1, 1), (0, 2), (1, 3)])
+def test_cpr_apply_matches(dev, orc, form, ncyc):
     w = workloads.make_small()
     mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(
-        dev, orc, w, 2, orc.cpr_opts(form=form), dev.cpr_opts(form=form))
+        dev, orc, w, 2, orc.cpr_opts(form=form, amg_cycles=ncyc),
+        dev.cpr_opts(form=form, amg_cycles=ncyc))
     rng = np.random.default_rng(2)
     f = rng.standard_normal(mo.N)
     f[2 * mo.n + 1::2] = 0.0

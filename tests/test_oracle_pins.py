@@ -8,7 +8,9 @@ a wrong index or a transposed operand in the oracle fails:
 - the FPF preconditioner (Algorithm 2) with approximate stages, against its
   five steps replayed densely;
 - the multi-level AMG cycle (V-cycle and K-cycle), against a dense replay
-  built from the exported level matrices, l1 diagonals and aggregates;
+  built from the exported level matrices, l1 diagonals and aggregates, and
+  the two-stage preconditioner with two and three AMG cycles per pressure
+  stage against the same replay;
 - RAS on 4x4 tiles at overlap 1 and 2: the overlapped sets against a
   breadth-first search of the block graph from the tile definition, the
   factors against the ILU(0) pattern identity per subdomain, and the apply
@@ -48,7 +50,7 @@ def test_fpf_approximate_stages_dense_replay(oracle_lib, exact_amg):
     m, x, J, b = _system(oracle_lib, w, steps=2)
     n = m.n
     Ad, _ = oracle_lib.decouple(J, b, n, oracle_lib.DEC_QI)
-    opts = oracle_lib.cpr_opts(form=oracle_lib.CPR_FPF, px=2, py=2,
+    opts = oracle_lib.cpr_opts(form=oracle_lib.CPR_FPF, px=2, py=2, amg_cycles=1,
                                max_coarse=10 ** 6 if exact_amg else 100)
     P = oracle_lib.Cpr(Ad, m, x, opts)
     A = Ad.to_scipy().tocsr()
@@ -129,6 +131,53 @@ def test_amg_cycle_dense_replay(oracle_lib, kcycle):
         ref = _dense_cycle(levels, 0, r, kcycle)
         got = H.vcycle(r)
         assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def _dense_levels(H):
+    levels = []
+    for l in range(H.nlev):
+        lv = H.level(l)
+        A = lv["A"].to_scipy().toarray()
+        entry = dict(A=A, l1=np.abs(A).sum(axis=1))
+        if l < H.nlev - 1:
+            P = np.zeros((A.shape[0], H.level(l + 1)["A"].n))
+            P[np.arange(A.shape[0]), lv["agg"]] = 1.0
+            entry["P"] = P
+        levels.append(entry)
+    return levels
+
+
+@pytest.mark.parametrize("ncyc", [2, 3])
+def test_two_stage_with_several_amg_cycles_dense_replay(oracle_lib, ncyc):
+    """Pressure stage of ncyc AMG cycles, each on the last residual:
+    x_p = C(r_p), then x_p += C(r_p - A_pp x_p); then x = Pi_p x_p,
+    r = f - A x, x += R^-1 r (the two-stage form)."""
+    w = workloads.make_small()
+    m, x, J, b = _system(oracle_lib, w, steps=2)
+    n = m.n
+    Ad, _ = oracle_lib.decouple(J, b, n, oracle_lib.DEC_QI)
+    kw = dict(px=2, py=2, max_coarse=40, kcycle=1)
+    P = oracle_lib.Cpr(Ad, m, x, oracle_lib.cpr_opts(amg_cycles=ncyc, **kw))
+    P1 = oracle_lib.Cpr(Ad, m, x, oracle_lib.cpr_opts(amg_cycles=1, **kw))
+    App = oracle_lib.extract_pressure(Ad, n)
+    H = oracle_lib.Amg(App, max_coarse=40, kcycle=1)
+    assert H.nlev >= 4
+    levels = _dense_levels(H)
+    A = Ad.to_scipy().tocsr()
+    Ap = levels[0]["A"]
+    f = np.random.default_rng(11).standard_normal(m.N)
+    f[2 * n + 1::2] = 0.0
+    fp = f[0:2 * n:2]
+    xp = _dense_cycle(levels, 0, fp, 1)
+    for _ in range(ncyc - 1):
+        xp = xp + _dense_cycle(levels, 0, fp - Ap @ xp, 1)
+    y = np.zeros(m.N)
+    y[0:2 * n:2] = xp
+    y = y + P.ras_apply(f - A @ y)
+    z = P.apply(f)
+    assert np.linalg.norm(z - y) <= 1e-11 * np.linalg.norm(y)
+    # the extra cycles matter
+    assert np.linalg.norm(P1.apply(f) - z) > 1e-6 * np.linalg.norm(z)
 
 
 def _fgmres_count(A, b, M, rtol=1e-8, maxit=200):
