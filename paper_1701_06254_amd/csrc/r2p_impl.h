@@ -191,6 +191,7 @@ struct RasDyn {
     DBuf<int> sub_nlev;                   // ns
     DBuf<int> counters;                   // scratch
     DBuf<int> prog;                       // ns: sweep progress read by the prefetch helpers
+    DBuf<int> swin;                       // ns: ring window of every subdomain's sweep
     RasFactors<double> f64;
     RasFactors<float> f32;
 };

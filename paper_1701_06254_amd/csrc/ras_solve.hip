@@ -21,7 +21,9 @@
 // requested three and four steps ahead; the y values its rows need that
 // were finished two steps earlier are requested then; the rest were
 // finished in the last few levels and are read from an LDS ring that holds
-// the results of the most recent rows.  One CU streams a subdomain's factors
+// the results of the most recent rows.  Which of these applies to an entry
+// follows from the fixed schedule, so the set-up marks it in the entry's
+// column.  One CU streams a subdomain's factors
 // at the rate its outstanding L2 misses allow, so helper workgroups of the
 // same launch, placed on the subdomain's XCD, read the static data of the
 // slices some levels ahead of the sweep into that XCD's L2; the sweep then
@@ -49,8 +51,16 @@ struct Sweep {
 constexpr int LK = 4;                  // sweep: slot pairs per round of a long (well) row
 constexpr int MAXK = 2;                // entries per lane held in registers (two lanes per row)
 constexpr int RAS_PAD = MAXK * RAS_SLICE;   // padding after the entry arrays: every task reads MAXK slot pairs
-constexpr int MAXLEV = 4096;           // levels per subdomain kept in LDS
+constexpr int MAXLEV = 4096;           // levels per subdomain (set-up limit)
 constexpr int PROG_STRIDE = 64;        // ints between two sweeps' progress counters
+// A factor entry's column (local position, < 2^28) carries in its top bits
+// where the sweep finds that column's y value (set after the factorisation):
+constexpr int COL_BITS = 28;
+constexpr int COL_MASK = (1 << COL_BITS) - 1;
+constexpr int F_RING = 0;              // the LDS ring (finished in the last levels)
+constexpr int F_PRE = 1;               // loaded from y two steps before the task runs
+constexpr int F_SLOW = 2;              // loaded from y when the task runs (rare)
+// padding entries are -1: their top bits read as 15
 
 // True when global row h precedes global row g in the local order.
 __device__ __forceinline__ bool before(int h, int g, int n, int order, const double *phi) {
@@ -729,7 +739,7 @@ struct Vec4 {
 // issued arrive in yf.  st .. L are uniform.
 template <class T>
 struct Task {
-    int st, cn, w, b, L, pf;
+    int st, cn, w, b, L;
     T a, d0, d1;
     T v[MAXK][4];
     T yf[MAXK][2];
@@ -784,24 +794,18 @@ __device__ __forceinline__ void load_task(Task<T> &R, const SweepArgs<T> &A, int
     }
 }
 
-// Load the y values of the entries of a task whose rows were finished when
-// the prefetch is issued (forward: before position `bound`, backward: from
-// `bound` on) and that will not be in the LDS ring when the task runs (the
-// ring window of the task's level); the task records the bound.
+// Load the y values of the task's entries marked F_PRE: finished before the
+// level the wavefront is at when it issues this load (two steps before the
+// task) and outside the LDS ring's window of the task's level.
 template <class T, bool FWD>
-__device__ __forceinline__ void prefetch_y(Task<T> &R, const int (&c)[MAXK], const T *y, int mtot,
-                                           int bound, const int *lp, int win) {
+__device__ __forceinline__ void prefetch_y(Task<T> &R, const int (&c)[MAXK], const T *y) {
     typedef typename Vec2<T>::type V2;
-    R.pf = bound;
-    int wl = FWD ? lp[R.L + 1] - win : lp[R.L] + win;
 #pragma unroll
     for (int k = 0; k < MAXK; k++) {
-        int q = c[k];
-        bool far = k < R.w && q >= 0 && q < mtot &&
-                   (FWD ? q < bound && q < wl : q >= bound && q >= wl);
+        bool far = k < R.w && ((unsigned)c[k] >> COL_BITS) == (unsigned)F_PRE;
         // only the lanes with such an entry load (a few per task)
         if (far) {
-            V2 v = *(const V2 *)&y[2 * (long)q];
+            V2 v = *(const V2 *)&y[2 * (long)(c[k] & COL_MASK)];
             R.yf[k][0] = v.x;
             R.yf[k][1] = v.y;
         }
@@ -818,7 +822,7 @@ __device__ __forceinline__ void prefetch_y(Task<T> &R, const int (&c)[MAXK], con
 // before its use, so the waits of a step are for loads issued two or more
 // steps earlier.
 template <class T, bool FWD, int U>
-__device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp, T *ring, int win,
+__device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, T *ring,
                                            int sa, int sb, int nlev, int wave, int lane, int nt, int k,
                                            Task<T> (&B)[4], int (&C)[4][MAXK], int4 (&M)[4],
                                            int &passed) {
@@ -837,32 +841,28 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
     // and nothing of the sweep's results depends on when they see it.
     __hip_atomic_store(&A.prog[PROG_STRIDE * blockIdx.x], (FWD ? 0 : nlev) + passed,
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    int lo = lp[cur.L], hi = lp[cur.L + 1];
-    // entries of task k+2 finished by now and outside its ring window
-    prefetch_y<T, FWD>(B[(U + 2) & 3], C[(U + 2) & 3], A.y, A.mtot, FWD ? lo : hi, lp, win);
-    // task k's entries not prefetched: from the ring, else from y
+    // marked entries of task k+2 (finished by now, outside its ring window)
+    prefetch_y<T, FWD>(B[(U + 2) & 3], C[(U + 2) & 3], A.y);
+    // task k's other entries: from the ring, or (rare) from y
     T y0[MAXK], y1[MAXK];
     bool on[MAXK];
     bool slow = false;
 #pragma unroll
     for (int kk = 0; kk < MAXK; kk++) {
-        int q = C[U][kk];
-        on[kk] = kk < cur.w && q >= 0 && q < A.mtot;
-        bool inwin = FWD ? q >= hi - win : q < lo + win;
-        bool pre = (FWD ? q < cur.pf : q >= cur.pf) && !inwin;
-        V2 rv = *(const V2 *)&ring[2 * (q & (R - 1))];
-        y0[kk] = pre ? cur.yf[kk][0] : rv.x;
-        y1[kk] = pre ? cur.yf[kk][1] : rv.y;
-        slow |= on[kk] && !pre && !inwin;
+        int c = C[U][kk];
+        unsigned f = (unsigned)c >> COL_BITS;
+        on[kk] = kk < cur.w && c >= 0;
+        V2 rv = *(const V2 *)&ring[2 * (c & (R - 1))];
+        y0[kk] = f == (unsigned)F_PRE ? cur.yf[kk][0] : rv.x;
+        y1[kk] = f == (unsigned)F_PRE ? cur.yf[kk][1] : rv.y;
+        slow |= on[kk] && f == (unsigned)F_SLOW;
     }
     if (__builtin_amdgcn_read_exec() & __ballot(slow)) {
 #pragma unroll
         for (int kk = 0; kk < MAXK; kk++) {
-            int q = C[U][kk];
-            bool inwin = FWD ? q >= hi - win : q < lo + win;
-            bool pre = (FWD ? q < cur.pf : q >= cur.pf) && !inwin;
-            if (on[kk] && !pre && !inwin) {
-                V2 v = *(const V2 *)&A.y[2 * (long)q];
+            int c = C[U][kk];
+            if (on[kk] && ((unsigned)c >> COL_BITS) == (unsigned)F_SLOW) {
+                V2 v = *(const V2 *)&A.y[2 * (long)(c & COL_MASK)];
                 y0[kk] = v.x;
                 y1[kk] = v.y;
             }
@@ -906,16 +906,15 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
             V4 bv[LK];
 #pragma unroll
             for (int j = 0; j < LK; j++) {
-                int qs = q[j] >= 0 && q[j] < A.mtot ? q[j] : 0;
+                int qs = q[j] >= 0 ? q[j] & COL_MASK : 0;
                 gv[j] = *(const V2 *)&A.y[2 * (long)qs];
                 rv[j] = *(const V2 *)&ring[2 * (qs & (R - 1))];
                 bv[j] = *(const V4 *)&vals[4 * idx[j]];
             }
 #pragma unroll
             for (int j = 0; j < LK; j++) {
-                bool ok = k0 + j < cur.w && q[j] >= 0 && q[j] < A.mtot;
-                int qs = ok ? q[j] : 0;
-                bool inwin = FWD ? qs >= hi - win : qs < lo + win;
+                bool ok = k0 + j < cur.w && q[j] >= 0;
+                bool inwin = ((unsigned)q[j] >> COL_BITS) == (unsigned)F_RING;
                 T a0 = inwin ? rv[j].x : gv[j].x, a1 = inwin ? rv[j].y : gv[j].y;
                 T e0 = bv[j].x * a0 + bv[j].y * a1;
                 T e1 = bv[j].z * a0 + bv[j].w * a1;
@@ -942,7 +941,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, const int *lp,
 // backward (U, then the inverse diagonal block).  Every wavefront passes one
 // workgroup barrier per level, in the same sequence, wherever it has work.
 template <class T, bool FWD>
-__device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *lp, T *ring, int win,
+__device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, T *ring,
                                           int sa, int sb, int nlev, int wave, int lane) {
     int nsl = sb - sa;
     constexpr int NCW = Sweep<T>::ncw;
@@ -961,8 +960,6 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *lp, 
         for (int j = 0; j < 3; j++) load_task<T, FWD>(B[j], A, M[j], lane);
         M[0] = meta[task_slice<FWD, Sweep<T>::ncw>(sa, sb, wave, 4, nt)];
         M[1] = meta[task_slice<FWD, Sweep<T>::ncw>(sa, sb, wave, 5, nt)];
-        // nothing is finished before the first two tasks
-        B[0].pf = B[1].pf = FWD ? lp[0] : lp[nlev];
         // enter the loop with nothing in flight, so that the wait counts the
         // compiler derives at its head follow the steady state
         __builtin_amdgcn_s_waitcnt(0);
@@ -972,10 +969,10 @@ __device__ __forceinline__ void sweep_dir(const SweepArgs<T> &A, const int *lp, 
         // it stores the same values again.  With no exit inside the unrolled
         // body the wait counts at every step follow the steady state.
         for (int k = 0; k < nt; k += 4) {
-            sweep_step<T, FWD, 0>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k, B, C, M, passed);
-            sweep_step<T, FWD, 1>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k + 1, B, C, M, passed);
-            sweep_step<T, FWD, 2>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k + 2, B, C, M, passed);
-            sweep_step<T, FWD, 3>(A, lp, ring, win, sa, sb, nlev, wave, lane, nt, k + 3, B, C, M, passed);
+            sweep_step<T, FWD, 0>(A, ring, sa, sb, nlev, wave, lane, nt, k, B, C, M, passed);
+            sweep_step<T, FWD, 1>(A, ring, sa, sb, nlev, wave, lane, nt, k + 1, B, C, M, passed);
+            sweep_step<T, FWD, 2>(A, ring, sa, sb, nlev, wave, lane, nt, k + 2, B, C, M, passed);
+            sweep_step<T, FWD, 3>(A, ring, sa, sb, nlev, wave, lane, nt, k + 3, B, C, M, passed);
         }
     }
     while (passed < nlev) {
@@ -1061,8 +1058,6 @@ __device__ unsigned prefetch_dir(const SweepArgs<T> &A, int s, int j, int H, int
 template <class T>
 __global__ __launch_bounds__(Sweep<T>::wg) void k_ras_sweep(SweepArgs<T> A) {
     constexpr int R = RingSize<T>::rows;
-    __shared__ int lp[MAXLEV + 1];
-    __shared__ int maxw;
     __shared__ __attribute__((aligned(16))) T ring[2 * R];
     if ((int)blockIdx.x >= A.ns) {
         // a helper: subdomain (b - ns) mod ns, on the same XCD as its sweep
@@ -1077,22 +1072,69 @@ __global__ __launch_bounds__(Sweep<T>::wg) void k_ras_sweep(SweepArgs<T> A) {
     }
     int s = blockIdx.x;
     int nlev = A.nlev[s], base = A.lbase[s];
-    if (threadIdx.x == 0) maxw = 0;
     for (int i = threadIdx.x; i < 2 * R; i += Sweep<T>::wg) ring[i] = (T)0;
-    __syncthreads();
-    int mw = 0;
-    for (int L = threadIdx.x; L <= nlev; L += Sweep<T>::wg) {
-        lp[L] = A.lptr[base + L];
-        if (L < nlev) mw = max(mw, A.lptr[base + L + 1] - A.lptr[base + L]);
-    }
-    atomicMax(&maxw, mw);
     int sa = A.soff[base], sb = A.soff[base + nlev];
     __syncthreads();
-    int win = maxw <= R ? R : 0;
     int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
-    sweep_dir<T, true>(A, lp, ring, win, sa, sb, nlev, wave, lane);
-    sweep_dir<T, false>(A, lp, ring, win, sa, sb, nlev, wave, lane);
+    sweep_dir<T, true>(A, ring, sa, sb, nlev, wave, lane);
+    sweep_dir<T, false>(A, ring, sa, sb, nlev, wave, lane);
+}
+
+// Ring window of every subdomain: positions [end(L) - ring, end(L)) forward
+// ([start(L), start(L) + ring) backward) are still in the LDS ring while
+// level L runs when every level is narrower than the ring; else none is.
+__global__ void k_sub_window(const int *lbase, const int *nlevs, const int *lptr, int ring, int *win) {
+    __shared__ int mw;
+    int s = blockIdx.x, base = lbase[s], nlev = nlevs[s];
+    if (threadIdx.x == 0) mw = 0;
+    __syncthreads();
+    int m = 0;
+    for (int L = threadIdx.x; L < nlev; L += blockDim.x)
+        m = max(m, lptr[base + L + 1] - lptr[base + L]);
+    atomicMax(&mw, m);
+    __syncthreads();
+    if (threadIdx.x == 0) win[s] = mw <= ring ? ring : 0;
+}
+
+// Where the sweep finds each entry's y value, from the sweep's fixed
+// schedule (ncw wavefronts take a subdomain's slices in turn, forward from
+// the first, backward from the last; the early loads of task j are issued
+// at task j - 2 of the same wavefront, when every level before that task's
+// has finished): in the ring window of the entry's level -> F_RING; else
+// finished before that bound -> F_PRE; else F_SLOW.  One workgroup per
+// slice; the class goes into the column's top bits.
+template <bool FWD>
+__global__ void k_entry_class(int ns, const int *lbase, const int *nlevs, const int *soff,
+                              const int *lptr, const int *win, const int4 *meta, int *cols,
+                              int ncw) {
+    int sl = blockIdx.x;
+    int lo = 0, hi = ns - 1;                  // subdomain: the last one starting at or before sl
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (soff[lbase[mid]] <= sl) lo = mid; else hi = mid - 1;
+    }
+    int s = lo, base = lbase[s], nlev = nlevs[s];
+    int sa = soff[base], sb = soff[base + nlev];
+    if (sl < sa || sl >= sb) return;
+    int4 m = meta[sl];
+    int w = m.y >> 8, b = m.z, L = m.w;
+    int idx = FWD ? sl - sa : sb - 1 - sl;
+    int bound;
+    if (idx / ncw < 2) {
+        bound = FWD ? lptr[base] : lptr[base + nlev];      // nothing finished yet
+    } else {
+        int L2 = meta[FWD ? sl - 2 * ncw : sl + 2 * ncw].w;
+        bound = FWD ? lptr[base + L2] : lptr[base + L2 + 1];
+    }
+    int ws = win[s], lev0 = lptr[base + L], lev1 = lptr[base + L + 1];
+    for (int e = b + (int)threadIdx.x; e < b + w * RAS_SLICE; e += blockDim.x) {
+        int q = cols[e];
+        if (q < 0) continue;
+        bool inwin = FWD ? q >= lev1 - ws : q < lev0 + ws;
+        bool pre = (FWD ? q < bound : q >= bound) && !inwin;
+        cols[e] = q | ((inwin ? F_RING : (pre ? F_PRE : F_SLOW)) << COL_BITS);
+    }
 }
 
 __global__ void k_slice_meta(int nslice, const int *st, const int *cn, const int *wl,
@@ -1285,6 +1327,25 @@ int r2p_ras_setup(r2p_cpr *P, hipStream_t s) {
         R2P_TRY(P->t_rl.ensure(2L * mtot));
         R2P_HIP(hipMemsetAsync(P->t_ras.p, 0, sizeof(double) * 2 * (size_t)mtot, s));
     }
+    // entry classes for the sweep of the precision set up
+    {
+        bool f32 = P->o.precision == R2P_FP32;
+        int ring = f32 ? RingSize<float>::rows : RingSize<double>::rows;
+        int ncw = f32 ? Sweep<float>::ncw : Sweep<double>::ncw;
+        R2P_TRY(D.swin.ensure(ns));
+        k_sub_window<<<ns, 256, 0, s>>>(D.sub_lbase.p, D.sub_nlev.p, D.lptr_dev.p, ring, D.swin.p);
+        R2P_LAUNCH();
+        if (D.nslice > 0) {
+            k_entry_class<true><<<D.nslice, 64, 0, s>>>(ns, D.sub_lbase.p, D.sub_nlev.p, D.soff.p,
+                                                        D.lptr_dev.p, D.swin.p, D.meta_l.p,
+                                                        D.lcol.p, ncw);
+            R2P_LAUNCH();
+            k_entry_class<false><<<D.nslice, 64, 0, s>>>(ns, D.sub_lbase.p, D.sub_nlev.p, D.soff.p,
+                                                         D.lptr_dev.p, D.swin.p, D.meta_u.p,
+                                                         D.ucol.p, ncw);
+            R2P_LAUNCH();
+        }
+    }
     R2P_HIP(hipMemcpyAsync(hflag, P->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
     R2P_HIP(hipStreamSynchronize(s));
     P->ms_ras = r2p_now_ms() - t1;
@@ -1398,7 +1459,7 @@ extern "C" int r2p_ras_export(r2p_cpr *P, int sub, int *glob, int *level, unsign
             for (int e = 0; e < cnt; e++, k++) {
                 long idx = ras_entry(base, r, e);
                 if (erow) erow[k] = g[p];
-                if (ecol) ecol[k] = g[cc[idx]];
+                if (ecol) ecol[k] = g[cc[idx] & COL_MASK];
                 if (eval) memcpy(eval + 4 * k, vv.data() + 4 * idx, 4 * sizeof(double));
             }
         }
