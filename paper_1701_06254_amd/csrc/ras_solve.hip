@@ -703,6 +703,7 @@ struct SweepArgs {
     const int *lcol, *ucol;
     const T *lval, *uval, *dinv, *rl;
     T *y;
+    long lpad, upad;             // first entry of the L and U arrays' zero padding (columns -1)
     int *prog;                   // PROG_STRIDE ns: levels passed by each sweep (forward, then
                                  // nlev + backward), one counter per 256 bytes
     int mtot;                    // local rows over all subdomains: the extent of y
@@ -758,11 +759,12 @@ template <class T, bool FWD>
 __device__ __forceinline__ void load_cols(int (&c)[MAXK], const SweepArgs<T> &A, int4 m, int lane) {
     int w = __builtin_amdgcn_readfirstlane(m.y) >> 8, b = __builtin_amdgcn_readfirstlane(m.z);
     const int *cols = FWD ? A.lcol : A.ucol;
-    // slot pairs past the slice's own re-read its last pair (lines already
-    // requested); they are masked where used
+    // slot pairs past the slice's own read the arrays' padding (column -1,
+    // block 0), so they add nothing and need no mask
+    long pad = FWD ? A.lpad : A.upad;
 #pragma unroll
     for (int k = 0; k < MAXK; k++)
-        c[k] = cols[(long)b + (long)min(k, max(w - 1, 0)) * RAS_SLICE + lane];
+        c[k] = cols[(k < w ? (long)b + (long)k * RAS_SLICE : pad) + lane];
 }
 
 template <class T, bool FWD>
@@ -786,9 +788,10 @@ __device__ __forceinline__ void load_task(Task<T> &R, const SweepArgs<T> &A, int
         R.d1 = d.y;
     }
     const T *vals = FWD ? A.lval : A.uval;
+    long pad = FWD ? A.lpad : A.upad;
 #pragma unroll
     for (int k = 0; k < MAXK; k++) {
-        long e = (long)R.b + (long)min(k, max(R.w - 1, 0)) * RAS_SLICE + lane;
+        long e = (k < R.w ? (long)R.b + (long)k * RAS_SLICE : pad) + lane;
         V4 v = *(const V4 *)&vals[4 * e];
         R.v[k][0] = v.x; R.v[k][1] = v.y; R.v[k][2] = v.z; R.v[k][3] = v.w;
     }
@@ -802,7 +805,7 @@ __device__ __forceinline__ void prefetch_y(Task<T> &R, const int (&c)[MAXK], con
     typedef typename Vec2<T>::type V2;
 #pragma unroll
     for (int k = 0; k < MAXK; k++) {
-        bool far = k < R.w && ((unsigned)c[k] >> COL_BITS) == (unsigned)F_PRE;
+        bool far = ((unsigned)c[k] >> COL_BITS) == (unsigned)F_PRE;
         // only the lanes with such an entry load (a few per task)
         if (far) {
             V2 v = *(const V2 *)&y[2 * (long)(c[k] & COL_MASK)];
@@ -845,23 +848,21 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, T *ring,
     prefetch_y<T, FWD>(B[(U + 2) & 3], C[(U + 2) & 3], A.y);
     // task k's other entries: from the ring, or (rare) from y
     T y0[MAXK], y1[MAXK];
-    bool on[MAXK];
     bool slow = false;
 #pragma unroll
     for (int kk = 0; kk < MAXK; kk++) {
         int c = C[U][kk];
         unsigned f = (unsigned)c >> COL_BITS;
-        on[kk] = kk < cur.w && c >= 0;
         V2 rv = *(const V2 *)&ring[2 * (c & (R - 1))];
         y0[kk] = f == (unsigned)F_PRE ? cur.yf[kk][0] : rv.x;
         y1[kk] = f == (unsigned)F_PRE ? cur.yf[kk][1] : rv.y;
-        slow |= on[kk] && f == (unsigned)F_SLOW;
+        slow |= f == (unsigned)F_SLOW;
     }
     if (__builtin_amdgcn_read_exec() & __ballot(slow)) {
 #pragma unroll
         for (int kk = 0; kk < MAXK; kk++) {
             int c = C[U][kk];
-            if (on[kk] && ((unsigned)c >> COL_BITS) == (unsigned)F_SLOW) {
+            if (((unsigned)c >> COL_BITS) == (unsigned)F_SLOW) {
                 V2 v = *(const V2 *)&A.y[2 * (long)(c & COL_MASK)];
                 y0[kk] = v.x;
                 y1[kk] = v.y;
@@ -882,8 +883,9 @@ __device__ __forceinline__ void sweep_step(const SweepArgs<T> &A, T *ring,
     for (int kk = 0; kk < MAXK; kk++) {
         T d0 = cur.v[kk][0] * y0[kk] + cur.v[kk][1] * y1[kk];
         T d1 = cur.v[kk][2] * y0[kk] + cur.v[kk][3] * y1[kk];
-        t0 -= on[kk] ? d0 : (T)0;
-        t1 -= on[kk] ? d1 : (T)0;
+        // padding entries hold a zero block (their y, from the ring, is finite)
+        t0 -= d0;
+        t1 -= d1;
     }
     if (cur.w > MAXK) {
         // rows with more than 2 MAXK entries (well rows and a few others): the
@@ -1370,6 +1372,8 @@ static int ras_solve_t(r2p_cpr *P, const double *r, double *out, const double *x
     A.lcol = D.lcol.p; A.ucol = D.ucol.p;
     A.lval = F.lval.p; A.uval = F.uval.p; A.dinv = F.dinv.p; A.rl = rl; A.y = y;
     A.mtot = mtot;
+    A.lpad = D.nlent;
+    A.upad = D.nuent;
     A.ns = ns;
     A.prog = D.prog.p;
     // helpers only where they fit beside the sweeps and share their XCDs
