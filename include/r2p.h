@@ -123,7 +123,8 @@ typedef struct {
     int status;        /* return code of the solve */
     double relres;     /* true ||D^-1(b - A y)|| / ||D^-1 b|| at exit */
     double ms_total;   /* host wall time of the call */
-    int reorth;        /* Gram-Schmidt passes repeated (selective second pass) */
+    int reorth;        /* second Gram-Schmidt passes (delayed by one iteration for restarts
+                          up to 32, else selective) */
 } r2p_solve_info;
 
 enum { R2P_FORCING_FIXED = 0, R2P_FORCING_EW = 1 };
@@ -281,7 +282,8 @@ int r2p_ras_export(r2p_cpr *P, int s, int *glob_host, int *level_host, unsigned 
 /* Solve A y = b for the Jacobian J (original, not decoupled, right-hand
  * side; D^-1 is applied inside: D^-1 A y = D^-1 b, Eq 29) by right
  * preconditioned flexible GMRES(restart) from y = 0 with the CPR
- * preconditioner P.  Classical Gram-Schmidt with a selective second pass;
+ * preconditioner P.  Classical Gram-Schmidt run twice, the second pass
+ * delayed by one iteration (restart <= 32; selective second pass above);
  * convergence on the true residual of the decoupled system.
  * o->method = R2P_KRYLOV_BICGSTAB instead runs right-preconditioned
  * BiCGSTAB (the second Krylov solver of the numerical experiments, two CPR

@@ -5,14 +5,23 @@
 // restarted GMRES as the Krylov solver ("Numerical experiments", Examples
 // 4-5), and "Nonlinear methods" (Algorithm 1, forcing terms of Eq 26).
 //
-// Device design.  The Arnoldi process is classical Gram-Schmidt: one pass
-// computes every projection h = V^T w and w.w together (fused multi-dot with
-// a fixed-order two-stage reduction), a second pass forms the new basis
-// vector (w - V h) / ||w - V h|| with the norm from Pythagoras.  When the
-// projection removes more than half of ||w||^2 the pass is repeated once
-// (selective reorthogonalisation, Daniel-Gragg-Kaufman-Stewart criterion).
-// The (m+1) x m Hessenberg matrix and its Givens rotations live on the host;
-// each iteration reads back one column.
+// Device design.  The Arnoldi process is classical Gram-Schmidt run twice,
+// with the second pass delayed by one iteration (DCGS2: Bielich, Langou,
+// Thomas, Swirydowicz, Yamazaki and Boman, "Low-synch Gram-Schmidt with
+// delayed reorthogonalization for Krylov solvers", Parallel Computing 2022).
+// At iteration j the basis vector v_j has had one projection only.  One pass
+// over the basis computes V^T w, w.w, V^T v_j and v_j.v_j together (fused
+// multi-dot, fixed-order two-stage reduction, one read-back); the host then
+// finishes v_j's second projection (its coefficients, its norm by
+// Pythagoras, and the correction this makes to Hessenberg column j - 1) and
+// w's first one; a second pass applies both, v_j <- (v_j - V s) / n_j and
+// v_{j+1} <- (w - V h) / ||w - V h||, reading each basis vector once.  The
+// flexible method keeps z_j = M v_j as computed: A Z = V H still holds with
+// the corrected basis.  For restarts above 32 (where the fused pass would
+// need too many registers) the second projection is done in the same
+// iteration, when the first removes more than half of ||w||^2
+// (Daniel-Gragg-Kaufman-Stewart criterion).  The (m+1) x m Hessenberg matrix
+// and its Givens rotations live on the host.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -27,6 +36,8 @@ int r2p_newton_update(r2p_model *m, const double *y, double *x, double ds_max, h
 
 constexpr int BS = 256;
 constexpr int MAXV = 65;                // basis vectors + 1 (w.w)
+constexpr int DCGS_MAX = 32;            // restarts up to this use the delayed second pass
+constexpr int MAXG = 2 * DCGS_MAX + 1;  // values of the fused pass: V^T w, w.w, V^T v_j
 constexpr int MDOT_BLOCKS = 1024;       // workgroups of the multi-dot (grid-stride over rows)
 
 // ----------------------------------------------------------- multi-dot
@@ -108,7 +119,7 @@ __global__ __launch_bounds__(BS) void k_mdot(const double *V, long ld, int nv, c
 }
 
 __global__ __launch_bounds__(BS) void k_mdot_sum(int nv, int nb, const double *part, double *h) {
-    __shared__ double red[BS / 64][MAXV];
+    __shared__ double red[BS / 64][MAXG > MAXV ? MAXG : MAXV];
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     // KT values of k at a time: their loads are in flight together
     constexpr int KT = 8;
@@ -149,6 +160,94 @@ __global__ __launch_bounds__(BS) void k_mupdate(const double *V, long ld, int nv
     double t = w[i];
     for (int k = 0; k < nv; k++) t -= hs[k] * V[(long)k * ld + i];
     out[i] = t * scale;
+}
+
+// The fused pass of the delayed second projection, nv = j + 1 basis vectors
+// (the last, v_j, projected once so far): values k < nv are V_k . w, nv is
+// w . w, nv + 1 + k (k < nv) are V_k . v_j; partials as in k_mdot.
+template <int NV>
+__global__ __launch_bounds__(BS) void k_mdot2(const double *V, long ld, int nv, const double *w,
+                                              long N, double *part) {
+    __shared__ double red[BS / 64][2 * NV + 1];
+    double acc[NV + 1], acg[NV];
+#pragma unroll
+    for (int k = 0; k <= NV; k++) acc[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; k++) acg[k] = 0.0;
+    long stride = (long)gridDim.x * 2 * BS;
+    const double *vl = V + (long)(nv - 1) * ld;
+    for (long i0 = (long)blockIdx.x * 2 * BS + threadIdx.x; i0 < N; i0 += stride) {
+        long i1 = i0 + BS;
+        bool two = i1 < N;
+        double w0 = w[i0], w1 = two ? w[i1] : 0.0;
+        double a[NV], b[NV];
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            const double *vk = k < nv ? V + (long)k * ld : vl;
+            a[k] = vk[i0];
+            b[k] = two ? vk[i1] : 0.0;
+        }
+        // v_j's values, picked from the loaded ones (no indexed registers)
+        double q0 = 0.0, q1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            q0 = k == nv - 1 ? a[k] : q0;
+            q1 = k == nv - 1 ? b[k] : q1;
+        }
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            acc[k] += a[k] * w0 + b[k] * w1;
+            acg[k] += a[k] * q0 + b[k] * q1;
+        }
+        acc[NV] += w0 * w0 + w1 * w1;
+    }
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int nb = gridDim.x;
+#pragma unroll
+    for (int k = 0; k <= NV; k++) {
+        if (k < nv || k == NV) {
+            double v = acc[k];
+            for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+            if (lane == 0) red[wid][k < nv ? k : nv] = v;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        if (k < nv) {
+            double v = acg[k];
+            for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+            if (lane == 0) red[wid][nv + 1 + k] = v;
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k <= 2 * nv; k += BS) {
+        double t = 0.0;
+        for (int q = 0; q < BS / 64; q++) t += red[q][k];
+        part[(long)k * nb + blockIdx.x] = t;
+    }
+}
+
+// The second pass of iteration j: v_j <- (v_j - sum_k s_k V_k) / n_j in
+// place, then out <- (w - sum_k h_k V_k - h_j v_j) / ||.|| (k < j), each
+// basis vector read once.
+struct Coef2 {
+    double s[DCGS_MAX], h[DCGS_MAX];
+    double hj, inv_nj, inv_hn;
+};
+__global__ __launch_bounds__(BS) void k_mupdate2(double *V, long ld, int j, Coef2 c,
+                                                 const double *w, long N, double *out) {
+    long i = (long)blockIdx.x * BS + threadIdx.x;
+    if (i >= N) return;
+    double vj = V[(long)j * ld + i], t = w[i];
+    for (int k = 0; k < j; k++) {
+        double vk = V[(long)k * ld + i];
+        vj -= c.s[k] * vk;
+        t -= c.h[k] * vk;
+    }
+    vj *= c.inv_nj;
+    V[(long)j * ld + i] = vj;
+    t -= c.hj * vj;
+    out[i] = t * c.inv_hn;
 }
 
 struct Coef {
@@ -238,6 +337,29 @@ static int mdot(Krylov &K, const double *V, int nv, double *w, long N, hipStream
         R2P_HIP(hipStreamSynchronize(s));
         memcpy(hhost, K.pin.p, sizeof(double) * (nv + 1));
     }
+    return 0;
+}
+
+// The fused pass of the delayed second projection: out[0..nv) = V^T w,
+// out[nv] = w.w, out[nv + 1 + k] = V_k . V_{nv-1} (k < nv); one read-back.
+static int mdot2(Krylov &K, const double *V, int nv, const double *w, long N, hipStream_t s,
+                 double *out) {
+    int nb = std::max(1, std::min(MDOT_BLOCKS, r2p_blocks(N, 2 * BS)));
+    R2P_TRY(K.part.ensure((size_t)nb * MAXG));
+    if (nv <= 4) k_mdot2<4><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p);
+    else if (nv <= 8) k_mdot2<8><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p);
+    else if (nv <= 12) k_mdot2<12><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p);
+    else if (nv <= 16) k_mdot2<16><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p);
+    else if (nv <= 20) k_mdot2<20><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p);
+    else if (nv <= 24) k_mdot2<24><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p);
+    else if (nv <= 28) k_mdot2<28><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p);
+    else k_mdot2<32><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p);
+    R2P_LAUNCH();
+    k_mdot_sum<<<1, BS, 0, s>>>(2 * nv, nb, K.part.p, K.h.p);
+    R2P_LAUNCH();
+    R2P_HIP(hipMemcpyAsync(K.pin.p, K.h.p, sizeof(double) * (2 * nv + 1), hipMemcpyDeviceToHost, s));
+    R2P_HIP(hipStreamSynchronize(s));
+    memcpy(out, K.pin.p, sizeof(double) * (2 * nv + 1));
     return 0;
 }
 
@@ -512,8 +634,8 @@ extern "C" int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y
     R2P_TRY(K.Z.ensure((size_t)m * N));
     R2P_TRY(K.r.ensure(N));
     R2P_TRY(K.bd.ensure(N));
-    R2P_TRY(K.h.ensure(MAXV));
-    R2P_TRY(K.pin.ensure(sizeof(double) * MAXV * 2));
+    R2P_TRY(K.h.ensure(MAXG > MAXV ? MAXG : MAXV));
+    R2P_TRY(K.pin.ensure(sizeof(double) * (MAXG > MAXV ? MAXG : MAXV) * 2));
     R2P_TRY(r2p_decouple_rhs(J, b, K.bd.p, s));
     double hb[MAXV];
     R2P_TRY(mdot(K, nullptr, 0, K.bd.p, N, s, hb));
@@ -528,16 +650,42 @@ extern "C" int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y
     } else if (o->method == R2P_KRYLOV_BICGSTAB) {
         R2P_TRY(solve_bicgstab(J, P, K, bnorm, y, o, inf, status, s));
     } else {
-        std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m);
+        // Hr: the Hessenberg matrix as computed (the delayed second pass
+        // corrects its previous column); H: Hr after the Givens rotations,
+        // recomputed over columns 0..j at every iteration (g: the rotated
+        // right-hand side beta e_1)
+        std::vector<double> Hr((size_t)(m + 1) * m, 0.0), H((size_t)(m + 1) * m, 0.0);
+        std::vector<double> cs(m), sn(m), g(m + 1), yv(m);
         R2P_HIP(hipMemcpyAsync(K.r.p, K.bd.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
         double beta = bnorm;
         int total = 0;
         int nblk = r2p_blocks(N, BS);
+        const bool delayed = m <= DCGS_MAX;
+        auto rotate = [&](int jj) -> bool {
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            for (int c = 0; c <= jj; c++) {
+                for (int i = 0; i <= c + 1; i++) H[(size_t)i * m + c] = Hr[(size_t)i * m + c];
+                for (int i = 0; i < c; i++) {
+                    double a = H[(size_t)i * m + c], b = H[(size_t)(i + 1) * m + c];
+                    H[(size_t)i * m + c] = cs[i] * a + sn[i] * b;
+                    H[(size_t)(i + 1) * m + c] = -sn[i] * a + cs[i] * b;
+                }
+                double a = H[(size_t)c * m + c], b = H[(size_t)(c + 1) * m + c];
+                double den = sqrt(a * a + b * b);
+                if (den == 0.0 || den != den) return false;
+                cs[c] = a / den;
+                sn[c] = b / den;
+                H[(size_t)c * m + c] = den;
+                H[(size_t)(c + 1) * m + c] = 0.0;
+                g[c + 1] = -sn[c] * g[c];
+                g[c] = cs[c] * g[c];
+            }
+            return true;
+        };
         while (total < o->maxit) {
             k_mupdate<<<nblk, BS, 0, s>>>(nullptr, N, 0, K.h.p, K.r.p, N, 1.0 / beta, K.V.p);
             R2P_LAUNCH();
-            std::fill(g.begin(), g.end(), 0.0);
-            g[0] = beta;
             int k = 0;
             bool stop = false;
             for (int j = 0; j < m && total < o->maxit; j++) {
@@ -545,47 +693,68 @@ extern "C" int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y
                 double *w = K.V.p + (size_t)(j + 1) * N;
                 R2P_TRY(r2p_cpr_apply_impl(P, vj, zj, s));
                 R2P_TRY(r2p_spmv_impl(J, zj, w, nullptr, s));
-                double hh[MAXV];
-                R2P_TRY(mdot(K, K.V.p, j + 1, w, N, s, hh));
-                double ww = hh[j + 1], hs = 0.0;
-                for (int i = 0; i <= j; i++) hs += hh[i] * hh[i];
-                double wn2 = ww - hs;
-                double hn;
-                if (wn2 > 0.49 * ww) {
-                    hn = sqrt(wn2);
-                    k_mupdate<<<nblk, BS, 0, s>>>(K.V.p, N, j + 1, K.h.p, w, N, 1.0 / hn, w);
+                double hh[MAXV], hn;
+                if (delayed) {
+                    // t = V^T w, w.w, q = V^T v_j in one pass
+                    double gv[MAXG];
+                    R2P_TRY(mdot2(K, K.V.p, j + 1, w, N, s, gv));
+                    const double *t = gv, *q = gv + j + 2;
+                    double ww = gv[j + 1];
+                    Coef2 c{};
+                    double nj = 1.0, hj = t[j];
+                    if (j > 0) {
+                        // v_j's second projection: s = q[0..j), n_j^2 = v_j.v_j - |s|^2
+                        double ss = 0.0, st = 0.0;
+                        for (int i = 0; i < j; i++) { ss += q[i] * q[i]; st += q[i] * t[i]; }
+                        double nj2 = q[j] - ss;
+                        if (!(nj2 > 0.0)) { status = R2P_BREAKDOWN; stop = true; total++; break; }
+                        nj = sqrt(nj2);
+                        // A z_{j-1} = V h_{j-1} + h_{j,j-1} v_j before the correction
+                        double hsub = Hr[(size_t)j * m + j - 1];
+                        for (int i = 0; i < j; i++) Hr[(size_t)i * m + j - 1] += hsub * q[i];
+                        Hr[(size_t)j * m + j - 1] = hsub * nj;
+                        hj = (t[j] - st) / nj;
+                        for (int i = 0; i < j; i++) c.s[i] = q[i];
+                        inf.reorth++;
+                    }
+                    double hs = hj * hj;
+                    for (int i = 0; i < j; i++) { hh[i] = t[i]; hs += t[i] * t[i]; c.h[i] = t[i]; }
+                    hh[j] = hj;
+                    double wn2 = ww - hs;
+                    hn = wn2 > 0.0 ? sqrt(wn2) : 0.0;
+                    c.hj = hj;
+                    c.inv_nj = 1.0 / nj;
+                    c.inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
+                    k_mupdate2<<<nblk, BS, 0, s>>>(K.V.p, N, j, c, w, N, w);
                     R2P_LAUNCH();
                 } else {
-                    // second Gram-Schmidt pass
-                    inf.reorth++;
-                    double h2[MAXV];
-                    R2P_TRY(mdot(K, K.V.p, j + 1, w, N, s, h2, K.h.p));
-                    double hs2 = 0.0;
-                    for (int i = 0; i <= j; i++) { hh[i] += h2[i]; hs2 += h2[i] * h2[i]; }
-                    double wn = h2[j + 1] - hs2;
-                    hn = wn > 0.0 ? sqrt(wn) : 0.0;
-                    if (hn > 0.0) {
+                    R2P_TRY(mdot(K, K.V.p, j + 1, w, N, s, hh));
+                    double ww = hh[j + 1], hs = 0.0;
+                    for (int i = 0; i <= j; i++) hs += hh[i] * hh[i];
+                    double wn2 = ww - hs;
+                    if (wn2 > 0.49 * ww) {
+                        hn = sqrt(wn2);
                         k_mupdate<<<nblk, BS, 0, s>>>(K.V.p, N, j + 1, K.h.p, w, N, 1.0 / hn, w);
                         R2P_LAUNCH();
+                    } else {
+                        // second Gram-Schmidt pass
+                        inf.reorth++;
+                        double h2[MAXV];
+                        R2P_TRY(mdot(K, K.V.p, j + 1, w, N, s, h2, K.h.p));
+                        double hs2 = 0.0;
+                        for (int i = 0; i <= j; i++) { hh[i] += h2[i]; hs2 += h2[i] * h2[i]; }
+                        double wn = h2[j + 1] - hs2;
+                        hn = wn > 0.0 ? sqrt(wn) : 0.0;
+                        if (hn > 0.0) {
+                            k_mupdate<<<nblk, BS, 0, s>>>(K.V.p, N, j + 1, K.h.p, w, N, 1.0 / hn, w);
+                            R2P_LAUNCH();
+                        }
                     }
                 }
-                for (int i = 0; i <= j; i++) H[(size_t)i * m + j] = hh[i];
-                H[(size_t)(j + 1) * m + j] = hn;
-                for (int i = 0; i < j; i++) {
-                    double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-                    H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-                    H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-                }
-                double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
-                double den = sqrt(a * a + c * c);
+                for (int i = 0; i <= j; i++) Hr[(size_t)i * m + j] = hh[i];
+                Hr[(size_t)(j + 1) * m + j] = hn;
                 total++;
-                if (den == 0.0 || den != den) { status = R2P_BREAKDOWN; stop = true; break; }
-                cs[j] = a / den;
-                sn[j] = c / den;
-                H[(size_t)j * m + j] = den;
-                H[(size_t)(j + 1) * m + j] = 0.0;
-                g[j + 1] = -sn[j] * g[j];
-                g[j] = cs[j] * g[j];
+                if (!rotate(j)) { status = R2P_BREAKDOWN; stop = true; break; }
                 k = j + 1;
                 if (fabs(g[j + 1]) <= o->rtol * bnorm || hn == 0.0) break;
             }
