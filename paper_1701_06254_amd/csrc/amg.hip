@@ -833,7 +833,9 @@ __global__ void k_down0(Level0<T> A, T *x, T *r) {
 }
 
 // Post-smoothing of level 0 on the prolonged iterate x (= x + P xc).
-template <class T>
+// With ACC the result is added to xo (xo = xo + result, as a separate
+// addition would) instead of replacing it.
+template <class T, bool ACC>
 __global__ void k_up0(Level0<T> A, const T *x, double *xo) {
     int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
@@ -846,7 +848,8 @@ __global__ void k_up0(Level0<T> A, const T *x, double *xo) {
         j = j < 0 ? 0 : (j >= A.n ? A.n - 1 : j);
         s -= ld_stream(&A.v7[(long)sl * A.n + i]) * x[j];
     }
-    xo[i] = (double)(x[i] + s / A.l1[i]);
+    double v = (double)(x[i] + s / A.l1[i]);
+    xo[i] = ACC ? xo[i] + v : v;
 }
 
 // Coarsest solve x = A_c^-1 b with the stored inverse (column-major, so a
@@ -1039,6 +1042,7 @@ struct Cycle {
     r2p_cpr *P;
     hipStream_t s;
     int nl;
+    bool acc = false;            // add the result to xp (hierarchies of two or more levels)
     static const T *vals(AmgLevel &A) {
         if constexpr (sizeof(T) == 4) return A.f32.val.p; else return (const T *)A.val.p;
     }
@@ -1159,7 +1163,10 @@ struct Cycle {
         R2P_LAUNCH();
         R2P_TRY(restrict_to(0));
         R2P_TRY(correct(0));
-        k_up0<T><<<r2p_blocks(Z.n, BS), BS, 0, s>>>(Z, vx(A), xp);
+        if (acc)
+            k_up0<T, true><<<r2p_blocks(Z.n, BS), BS, 0, s>>>(Z, vx(A), xp);
+        else
+            k_up0<T, false><<<r2p_blocks(Z.n, BS), BS, 0, s>>>(Z, vx(A), xp);
         R2P_LAUNCH();
         return 0;
     }
@@ -1191,11 +1198,6 @@ __global__ void k_res0(Level0<T> A, const double *xp, double *r) {
     r[i] = s;
 }
 
-__global__ void k_add(int n, const double *c, double *x) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = x[i] + c[i];
-}
-
 // The pressure stage: amg_cycles cycles on A_pp xp = f_p from xp = 0, each
 // on the residual of the last (xp = C(f_p), then xp = xp + C(f_p - A_pp xp)).
 template <class T>
@@ -1213,9 +1215,10 @@ static int amg_apply_t(r2p_cpr *P, const double *f, int fstride, double *xp, hip
     for (int k = 1; k < P->o.amg_cycles; k++) {
         k_res0<T><<<r2p_blocks(A.n, BS), BS, 0, s>>>(Z, xp, P->t_ares.p);
         R2P_LAUNCH();
-        R2P_TRY(r2p_amg_cycle(P, P->t_ares.p, 1, P->t_acor.p, s));
-        k_add<<<r2p_blocks(A.n, BS), BS, 0, s>>>(A.n, P->t_acor.p, xp);
-        R2P_LAUNCH();
+        // the cycle's last kernel adds its result to xp
+        Cycle<T> c{P, s, P->nlev};
+        c.acc = true;
+        R2P_TRY(c.run(P->t_ares.p, 1, xp));
     }
     return 0;
 }

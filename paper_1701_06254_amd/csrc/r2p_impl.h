@@ -253,7 +253,7 @@ struct r2p_cpr {
     DBuf<int> piv;
     DBuf<double> kscal;      // K-cycle scalars {q1.q1, a1, beta, a2} per level
     DBuf<double> kpart;      // K-cycle dot-product partial sums
-    DBuf<double> t_ares, t_acor;   // pressure stage: residual and correction of the later cycles
+    DBuf<double> t_ares;           // pressure stage: residual for the later cycles
     DBuf<int> status;        // device status flags
     // level-0 structure cache, and the model the cached structures belong to
     int app_n = -1;

@@ -491,10 +491,7 @@ extern "C" int r2p_setup_cpr(r2p_jacobian *J, const r2p_cpr_opts *o, r2p_cpr *P,
     R2P_TRY(P->t_r.ensure(N));
     R2P_TRY(P->t_y.ensure(N));
     R2P_TRY(P->t_xp.ensure(ph.n));
-    if (o->amg_cycles > 1) {
-        R2P_TRY(P->t_ares.ensure(ph.n));
-        R2P_TRY(P->t_acor.ensure(ph.n));
-    }
+    if (o->amg_cycles > 1) R2P_TRY(P->t_ares.ensure(ph.n));
     P->ms_dec = P->ms_order = P->ms_ras = P->ms_amg = 0.0;
     double t0 = r2p_now_ms();
     R2P_TRY(r2p_decouple_jacobian(J, o->decouple, s));
