@@ -257,6 +257,22 @@ def test_fgmres_solve_matches(dev, orc, form):
     assert np.linalg.norm(bd - A @ yg) <= 1.000001e-8 * np.linalg.norm(bd)
 
 
+@pytest.mark.parametrize("restart", [8, 40])
+def test_fgmres_restart_lengths_match(dev, orc, restart):
+    """Restarts of 8 (the delayed second Gram-Schmidt pass over several
+    restart cycles per solve) and 40 (above its limit of 32: the selective
+    second pass) against the oracle's modified Gram-Schmidt FGMRES."""
+    w = workloads.make_small()
+    mo, x, Ad, bd, Po, mg, J, b, P = _setup_both(dev, orc, w, 3, orc.cpr_opts(), dev.cpr_opts())
+    yo, st, its_o, rr_o = orc.fgmres(Ad, bd, Po, restart=restart)
+    assert st == 0
+    yg, info = dev.solve(J, P, b, dev.solve_opts(restart=restart))
+    assert info.status == 0 and info.relres <= 1e-8
+    assert abs(info.iterations - its_o) <= 2
+    A = Ad.to_scipy()
+    assert np.linalg.norm(bd - A @ _h(yg)) <= 1.000001e-8 * np.linalg.norm(bd)
+
+
 @pytest.mark.parametrize("form", [0, 1])
 def test_bicgstab_solve_matches(dev, orc, form):
     """BiCGSTAB (two CPR applications per iteration) on the same system, with
