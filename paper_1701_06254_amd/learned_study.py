@@ -15,8 +15,9 @@ backward kernels.
 Evaluation: held-out seeds (from 9000), each run from its cold start
 through the controller without the network, then the same step lengths
 replayed with the network's prediction offered as the first Newton iterate
-under the library's rules (the scaled-residual rule, and the try rule);
-Newton and linear iterations and wall time are reported per form.
+under the library's rules (the scaled-residual rule, and the try rule), and
+again with only its water saturation offered (pressure and well unknowns
+from x^n); Newton and linear iterations and wall time are reported per form.
 
 Usage: python -m paper_1701_06254_amd.learned_study [--train-seeds 8]
 [--steps 12] [--crops 52] [--eval-seeds 10] [--iters 6000] [--out FILE.json]
@@ -97,7 +98,9 @@ def collect(seeds, nsteps, crops, opts, rng):
 
 def evaluate(net, seeds, nsteps, opts, rules):
     """Plain controller run, then replays of its accepted step lengths with
-    the network's first iterate under each rule."""
+    the network's first iterate under each rule.  A rule is (name, guess
+    rule, part): part "full" offers the network's iterate, "sw" offers x^n
+    with only the water saturation of the network's iterate."""
     import torch
     import workloads
     from . import r2p
@@ -119,7 +122,7 @@ def evaluate(net, seeds, nsteps, opts, rules):
                          "failed_steps": sum(1 for r in recs if r["status"] != 0),
                          "s": round(plain_s, 2)}}
         n = m.n
-        for name, rule in rules:
+        for name, rule, part in rules:
             o = r2p.newton_opts(cpr=opts.cpr, lin=opts.lin, guess_rule=rule)
             xl = x0.clone()
             nt = lt = taken = fails = 0
@@ -127,6 +130,10 @@ def evaluate(net, seeds, nsteps, opts, rules):
             t0 = time.perf_counter()
             for dt in dts:
                 guess = net.warm_start(m, xl, dt)
+                if part == "sw":
+                    g = xl.clone()
+                    g[1:2 * n:2] = guess[1:2 * n:2]
+                    guess = g
                 info = m.newton_step(xl, dt, o, x_guess=guess)
                 nt += info.newton_its
                 lt += info.linear_its
@@ -177,10 +184,13 @@ def main(argv=None):
     t_train = time.perf_counter() - t1
     if args.weights:
         np.save(args.weights, net.get_params())
-    rules = [("scaled_rule", r2p.GUESS_SCALED_INF), ("try_rule", r2p.GUESS_TRY)]
+    rules = [("scaled_rule", r2p.GUESS_SCALED_INF, "full"), ("try_rule", r2p.GUESS_TRY, "full"),
+             ("sw_scaled_rule", r2p.GUESS_SCALED_INF, "sw"), ("sw_try_rule", r2p.GUESS_TRY, "sw")]
     ev = evaluate(net, range(9000, 9000 + args.eval_seeds), args.steps, opts, rules)
     tot = {k: {"newton": sum(r[k]["newton"] for r in ev), "linear": sum(r[k]["linear"] for r in ev),
-               "s": round(sum(r[k]["s"] for r in ev), 2)} for k in ("plain", "scaled_rule", "try_rule")}
+               "guess_taken": sum(r[k].get("guess_taken", 0) for r in ev),
+               "s": round(sum(r[k]["s"] for r in ev), 2)}
+           for k in ("plain",) + tuple(r[0] for r in rules)}
     res = {"train_seeds": [1000, 1000 + args.train_seeds - 1], "pairs": len(data) // args.crops,
            "crops": len(data), "crop": [50, CROP, CROP], "adam_steps": args.iters,
            "data_s": round(t_data, 1), "train_s": round(t_train, 1),

@@ -78,7 +78,8 @@ def test_learned_start_at_2m_reports_iterations():
                              batch=4, lr=1e-3, seed=3)
     assert np.mean(losses[-20:]) < np.mean(losses[:20])
     del data
-    ev = learned_study.evaluate(net, [9000], 6, opts, [("scaled_rule", r2p.GUESS_SCALED_INF)])[0]
+    ev = learned_study.evaluate(net, [9000], 6, opts,
+                                [("scaled_rule", r2p.GUESS_SCALED_INF, "full")])[0]
     plain, learned = ev["plain"], ev["scaled_rule"]
     print(f"2M held-out seed 9000: Newton {plain['newton']} -> {learned['newton']}, GMRES "
           f"{plain['linear']} -> {learned['linear']}, guess taken {learned['guess_taken']} of "
