@@ -47,11 +47,12 @@ constexpr int MDOT_BLOCKS = 1024;       // workgroups of the multi-dot (grid-str
 // visit issues the loads of every vector together; the reductions happen
 // once, at the end: a fixed butterfly per wavefront, a fixed sum over the
 // wavefronts, one partial per workgroup and k (k-major).  k_mdot_sum (one
-// workgroup) adds the partials of every k, each thread over a fixed stride
+// workgroup per k) adds the partials of k, each thread over a fixed stride
 // of workgroups, then the same butterfly and wavefront sum, so the result
-// does not depend on scheduling.  (A last-workgroup ticket in one launch
-// would need a device-scope fence in every workgroup, which on this GPU
-// writes back and invalidates the L2.)
+// does not depend on scheduling; it also writes the values straight into
+// the pinned host buffer the solver reads after the stream synchronises.
+// (A last-workgroup ticket in one launch would need a device-scope fence in
+// every workgroup, which on this GPU writes back and invalidates the L2.)
 //
 // With UPD the launch first applies a Gram-Schmidt pass, w <- w - V h (h
 // from the previous multi-dot), row by row in the same order as k_mupdate,
@@ -118,34 +119,24 @@ __global__ __launch_bounds__(BS) void k_mdot(const double *V, long ld, int nv, c
     }
 }
 
-__global__ __launch_bounds__(BS) void k_mdot_sum(int nv, int nb, const double *part, double *h) {
-    __shared__ double red[BS / 64][MAXG > MAXV ? MAXG : MAXV];
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    // KT values of k at a time: their loads are in flight together
-    constexpr int KT = 8;
-    for (int k0 = 0; k0 <= nv; k0 += KT) {
-        double sum[KT];
-#pragma unroll
-        for (int u = 0; u < KT; u++) sum[u] = 0.0;
-        for (int b = threadIdx.x; b < nb; b += BS) {
-#pragma unroll
-            for (int u = 0; u < KT; u++) {
-                int k = k0 + u <= nv ? k0 + u : nv;
-                sum[u] += part[(long)k * nb + b];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < KT; u++) {
-            double v = sum[u];
-            for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-            if (lane == 0 && k0 + u <= nv) red[wid][k0 + u] = v;
-        }
-    }
+__global__ __launch_bounds__(BS) void k_mdot_sum(int nb, const double *part, double *h,
+                                                 double *hout) {
+    // one workgroup per value k; its sum in a fixed order: each thread over
+    // a fixed stride of the partials, a butterfly per wavefront, then the
+    // wavefronts in order
+    __shared__ double red[BS / 64];
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, k = blockIdx.x;
+    const double *pk = part + (long)k * nb;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BS) v += pk[b];
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0) red[wid] = v;
     __syncthreads();
-    for (int k = threadIdx.x; k <= nv; k += BS) {
+    if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int q = 0; q < BS / 64; q++) t += red[q][k];
+        for (int q = 0; q < BS / 64; q++) t += red[q];
         h[k] = t;
+        if (hout) hout[k] = t;
     }
 }
 
@@ -301,11 +292,21 @@ __global__ void k_undecouple(int n, long N, const double4 *dec, const double *rd
 struct Krylov {
     DBuf<double> V, Z, part, h, r, bd, w;
     HostPinned pin;
+    double *pin_dev = nullptr;        // device address of pin
     long N = 0;
     int m = 0;
 };
 
 static Krylov &krylov_for(r2p_cpr *P);
+
+// The pinned read-back buffer and its device address.
+static int pin_ensure(Krylov &K, size_t bytes) {
+    R2P_TRY(K.pin.ensure(bytes));
+    void *d = nullptr;
+    R2P_HIP(hipHostGetDevicePointer(&d, K.pin.p, 0));
+    K.pin_dev = (double *)d;
+    return 0;
+}
 
 // h = V^T w and w.w into K.h (and hhost); with upd (= K.h of the previous
 // projection) w first loses V upd in the same launch.
@@ -330,10 +331,9 @@ static int mdot(Krylov &K, const double *V, int nv, double *w, long N, hipStream
     else R2P_MDOT(64);
 #undef R2P_MDOT
     R2P_LAUNCH();
-    k_mdot_sum<<<1, BS, 0, s>>>(nv, nb, K.part.p, K.h.p);
+    k_mdot_sum<<<nv + 1, BS, 0, s>>>(nb, K.part.p, K.h.p, hhost ? K.pin_dev : nullptr);
     R2P_LAUNCH();
     if (hhost) {
-        R2P_HIP(hipMemcpyAsync(K.pin.p, K.h.p, sizeof(double) * (nv + 1), hipMemcpyDeviceToHost, s));
         R2P_HIP(hipStreamSynchronize(s));
         memcpy(hhost, K.pin.p, sizeof(double) * (nv + 1));
     }
@@ -355,9 +355,8 @@ static int mdot2(Krylov &K, const double *V, int nv, const double *w, long N, hi
     else if (nv <= 28) k_mdot2<28><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p);
     else k_mdot2<32><<<nb, BS, 0, s>>>(V, N, nv, w, N, K.part.p);
     R2P_LAUNCH();
-    k_mdot_sum<<<1, BS, 0, s>>>(2 * nv, nb, K.part.p, K.h.p);
+    k_mdot_sum<<<2 * nv + 1, BS, 0, s>>>(nb, K.part.p, K.h.p, K.pin_dev);
     R2P_LAUNCH();
-    R2P_HIP(hipMemcpyAsync(K.pin.p, K.h.p, sizeof(double) * (2 * nv + 1), hipMemcpyDeviceToHost, s));
     R2P_HIP(hipStreamSynchronize(s));
     memcpy(out, K.pin.p, sizeof(double) * (2 * nv + 1));
     return 0;
@@ -632,7 +631,7 @@ extern "C" int r2p_solve(r2p_jacobian *J, r2p_cpr *P, const double *b, double *y
     R2P_TRY(K.r.ensure(N));
     R2P_TRY(K.bd.ensure(N));
     R2P_TRY(K.h.ensure(MAXG > MAXV ? MAXG : MAXV));
-    R2P_TRY(K.pin.ensure(sizeof(double) * (MAXG > MAXV ? MAXG : MAXV) * 2));
+    R2P_TRY(pin_ensure(K, sizeof(double) * (MAXG > MAXV ? MAXG : MAXV) * 2));
     R2P_TRY(r2p_decouple_rhs(J, b, K.bd.p, s));
     double hb[MAXV];
     R2P_TRY(mdot(K, nullptr, 0, K.bd.p, N, s, hb));
@@ -928,7 +927,7 @@ extern "C" int r2p_newton_step(r2p_model *m, double *x, double dt, const double 
     R2P_HIP(hipMemcpyAsync(W->xk.p, x, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
     Krylov &K = krylov_for(W->P);
     R2P_TRY(K.h.ensure(MAXV));
-    R2P_TRY(K.pin.ensure(sizeof(double) * MAXV * 2));
+    R2P_TRY(pin_ensure(K, sizeof(double) * (MAXG > MAXV ? MAXG : MAXV) * 2));
     if (x_guess) {
         double ng = 0.0, n0 = 0.0, hb[2];
         int rc = 0;
