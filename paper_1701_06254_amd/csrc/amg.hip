@@ -978,7 +978,17 @@ __global__ __launch_bounds__(BS) void k_kspmv(CsrArgs<T> A, const T *q1, double 
 __global__ __launch_bounds__(1024) void k_kfin(int nb, const double *part, int step, double *ks) {
     __shared__ double red[2][1024 / 64];
     double s0 = 0.0, s1 = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) { s0 += part[b]; s1 += part[nb + b]; }
+    // eight strides of partials requested together, then added in the same
+    // order as one at a time (the result does not change)
+    int st = blockDim.x, b = threadIdx.x;
+    for (; b + 7 * st < nb; b += 8 * st) {
+        double a0[8], a1[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) { a0[u] = part[b + u * st]; a1[u] = part[nb + b + u * st]; }
+#pragma unroll
+        for (int u = 0; u < 8; u++) { s0 += a0[u]; s1 += a1[u]; }
+    }
+    for (; b < nb; b += st) { s0 += part[b]; s1 += part[nb + b]; }
     for (int d = 32; d > 0; d >>= 1) {
         s0 += __shfl_xor(s0, d, 64);
         s1 += __shfl_xor(s1, d, 64);

@@ -128,7 +128,16 @@ __global__ __launch_bounds__(BS) void k_mdot_sum(int nb, const double *part, dou
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, k = blockIdx.x;
     const double *pk = part + (long)k * nb;
     double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += BS) v += pk[b];
+    int b = threadIdx.x;
+    // four strides requested together, added in the same order
+    for (; b + 3 * BS < nb; b += 4 * BS) {
+        double a[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) a[u] = pk[b + u * BS];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v += a[u];
+    }
+    for (; b < nb; b += BS) v += pk[b];
     for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
     if (lane == 0) red[wid] = v;
     __syncthreads();
